@@ -1,0 +1,244 @@
+"""ctypes wrapper of the FP64 AMH oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the CPU
+baseline leg of ``bench.py``; never by the product package.  All arrays are
+numpy float64 / uint32 / uint8 in C order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+
+class Cfg(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32), ("n_bins", C.c_int32), ("d_min", C.c_double), ("bin_w", C.c_double),
+        ("window_d", C.c_int32), ("global_every", C.c_int32), ("anchor_every", C.c_int32),
+        ("pad0", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
+        ("total_sweeps", C.c_int64), ("seed", C.c_uint64),
+    ]
+
+
+class ReplayReport(C.Structure):
+    _fields_ = [
+        ("n_steps", C.c_int64), ("n_forks", C.c_int64), ("n_de_fail", C.c_int64),
+        ("n_delta_fail", C.c_int64), ("n_logic_fail", C.c_int64), ("first_fail_step", C.c_int64),
+        ("n_anchors", C.c_int64), ("n_anchor_fail", C.c_int64),
+        ("max_de_abs_err", C.c_double), ("max_de_rel_err", C.c_double),
+        ("max_anchor_rel_err", C.c_double), ("max_fork_margin", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_U32 = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_U8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def _opt(nd):
+    """ndpointer that also accepts None."""
+    class _P(nd):  # type: ignore[misc, valid-type]
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return super().from_param(obj)
+    return _P
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    L = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    L.oracle_philox4x32_10.argtypes = [_U32, _U32, _U32]
+    L.oracle_philox_batch.argtypes = [C.c_int64, _U32, _U32, _U32]
+    L.oracle_proposal.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_int32, C.c_double,
+                                  P(C.c_double), P(C.c_double)]
+    L.oracle_beta.argtypes = [P(Cfg), C.c_int64]
+    L.oracle_beta.restype = C.c_double
+    L.oracle_is_global.argtypes = [P(Cfg), C.c_int64]
+    L.oracle_is_global.restype = C.c_int32
+    L.oracle_nerf.argtypes = [C.c_int32, _D, _D]
+    L.oracle_geometry_constants.argtypes = [_D]
+    L.oracle_pair_energy.argtypes = [_D, C.c_int32, C.c_double, C.c_double, C.c_double]
+    L.oracle_pair_energy.restype = C.c_double
+    L.oracle_pair_energy_deriv.argtypes = [_D, C.c_int32, C.c_double, C.c_double, C.c_double]
+    L.oracle_pair_energy_deriv.restype = C.c_double
+    L.oracle_energy_full.argtypes = [P(Cfg), _D, _D]
+    L.oracle_energy_full.restype = C.c_double
+    L.oracle_energy_window.argtypes = [P(Cfg), _D, _D, C.c_int32]
+    L.oracle_energy_window.restype = C.c_double
+    L.oracle_neumaier_sum.argtypes = [C.c_int64, _D]
+    L.oracle_neumaier_sum.restype = C.c_double
+    L.oracle_delta_e.argtypes = [P(Cfg), _D, _D, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                 P(C.c_double)]
+    L.oracle_delta_e.restype = C.c_double
+    L.oracle_grad.argtypes = [P(Cfg), _D, _D, P(C.c_double), _D]
+    L.oracle_chain_init.argtypes = [P(Cfg), _D, C.c_int32, _D, _D, _D]
+    L.oracle_run.argtypes = [P(Cfg), _D, C.c_int32, _opt(_U32), C.c_int64, C.c_int64, C.c_int32,
+                             C.c_int32, _D, _D, _D, _I64, C.c_double, _opt(_D), _opt(_U8),
+                             _opt(_D)]
+    L.oracle_run.restype = C.c_int32
+    L.oracle_replay.argtypes = [P(Cfg), _D, C.c_uint32, _D, C.c_int64, C.c_int64, _D, _D, _U8,
+                                _opt(_D), C.c_double, C.c_double, C.c_double, _D,
+                                P(ReplayReport)]
+    L.oracle_replay.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def make_cfg(w) -> Cfg:
+    """Oracle config from a synthetic.Workload."""
+    return Cfg(L=w.L, n_bins=w.n_bins, d_min=w.d_min, bin_w=w.bin_w, window_d=w.window_d,
+               global_every=w.global_every, anchor_every=w.anchor_period, pad0=0,
+               sigma=w.sigma, T0=w.T0, T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------- #
+def philox(ctr, key) -> np.ndarray:
+    ctr = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    key = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty_like(ctr)
+    lib().oracle_philox_batch(ctr.shape[0], ctr, key, out)
+    return out
+
+
+def proposal(seed: int, chain: int, t: int, k: int, sigma: float) -> tuple[float, float]:
+    d, lu = C.c_double(), C.c_double()
+    lib().oracle_proposal(seed, chain, t, k, sigma, C.byref(d), C.byref(lu))
+    return d.value, lu.value
+
+
+def beta(cfg: Cfg, t: int) -> float:
+    return lib().oracle_beta(C.byref(cfg), t)
+
+
+def is_global(cfg: Cfg, t: int) -> bool:
+    return bool(lib().oracle_is_global(C.byref(cfg), t))
+
+
+def nerf(s) -> np.ndarray:
+    s = _f64(s)
+    L = s.shape[-1] // 2
+    out = np.empty((L, 4, 3))
+    lib().oracle_nerf(L, s, out)
+    return out
+
+
+def cb(s) -> np.ndarray:
+    return nerf(s)[:, 3, :].copy()
+
+
+def geometry_constants() -> np.ndarray:
+    out = np.empty(10)
+    lib().oracle_geometry_constants(out)
+    return out
+
+
+def pair_energy(y_row, d: float, d_min: float = 2.0, bin_w: float = 0.5) -> float:
+    y_row = _f64(y_row)
+    return lib().oracle_pair_energy(y_row, y_row.shape[0], d_min, bin_w, d)
+
+
+def pair_energy_deriv(y_row, d: float, d_min: float = 2.0, bin_w: float = 0.5) -> float:
+    y_row = _f64(y_row)
+    return lib().oracle_pair_energy_deriv(y_row, y_row.shape[0], d_min, bin_w, d)
+
+
+def energy_full(cfg: Cfg, y, atoms) -> float:
+    return lib().oracle_energy_full(C.byref(cfg), _f64(y), _f64(atoms))
+
+
+def energy(cfg: Cfg, y, s) -> float:
+    return energy_full(cfg, y, nerf(s))
+
+
+def energy_window(cfg: Cfg, y, atoms, k: int) -> float:
+    return lib().oracle_energy_window(C.byref(cfg), _f64(y), _f64(atoms), k)
+
+
+def neumaier_sum(x) -> float:
+    x = _f64(x)
+    return lib().oracle_neumaier_sum(x.shape[0], x)
+
+
+def delta_e(cfg: Cfg, y, s, k: int, delta: float, global_: bool, mode: int) -> tuple[float, float]:
+    S = C.c_double()
+    dE = lib().oracle_delta_e(C.byref(cfg), _f64(y), _f64(s), k, delta, int(global_), mode,
+                              C.byref(S))
+    return dE, S.value
+
+
+def grad(cfg: Cfg, y, s) -> tuple[float, np.ndarray]:
+    s = _f64(s)
+    g = np.empty_like(s)
+    V = C.c_double()
+    lib().oracle_grad(C.byref(cfg), _f64(y), s, C.byref(V), g)
+    return V.value, g
+
+
+class Chains:
+    """State of a set of oracle chains (s, s_best, V_anchor, V_best, counters)."""
+
+    def __init__(self, cfg: Cfg, y, s0, chain_ids=None):
+        self.cfg = cfg
+        self.y = _f64(y)
+        s0 = np.atleast_2d(_f64(s0))
+        self.C = s0.shape[0]
+        self.s = s0.copy()
+        self.s_best = s0.copy()
+        self.v = np.empty((self.C, 2))
+        lib().oracle_chain_init(C.byref(cfg), self.y, self.C, self.s, self.s_best, self.v)
+        self.counters = np.zeros((self.C, 4), dtype=np.int64)
+        self.counters[:, 2] = -1
+        self.ids = (np.arange(self.C, dtype=np.uint32) if chain_ids is None
+                    else np.ascontiguousarray(chain_ids, dtype=np.uint32))
+        self.t = 0
+
+    def run(self, n_sweeps: int, mode: int = 1, threads: int = 1, target: float = -math.inf,
+            log_steps: bool = False, log_anchors: bool = False):
+        n = 2 * self.cfg.L
+        A = self.cfg.anchor_every
+        na = (self.t + n_sweeps) // A - self.t // A
+        step_log = np.empty((self.C, n_sweeps * n, 2)) if log_steps else None
+        acc_log = np.empty((self.C, n_sweeps * n), dtype=np.uint8) if log_steps else None
+        anchor_log = np.empty((self.C, na)) if log_anchors else None
+        rc = lib().oracle_run(C.byref(self.cfg), self.y, self.C, self.ids, self.t, n_sweeps, mode,
+                              threads, self.s, self.s_best, self.v, self.counters, target,
+                              step_log, acc_log, anchor_log)
+        if rc != 0:
+            raise ValueError("oracle_run rejected its input")
+        self.t += n_sweeps
+        return step_log, acc_log, anchor_log
+
+
+def replay(cfg: Cfg, y, chain_id: int, s0, t_begin: int, n_sweeps: int, gpu_dE, gpu_delta,
+           gpu_acc, gpu_anchor=None, rel_tol: float = 1e-4, abs_tol: float = 1e-6,
+           anchor_rel_tol: float = 1e-4):
+    s_out = np.empty(2 * cfg.L)
+    rep = ReplayReport()
+    rc = lib().oracle_replay(C.byref(cfg), _f64(y), chain_id, _f64(s0), t_begin, n_sweeps,
+                             _f64(gpu_dE), _f64(gpu_delta),
+                             np.ascontiguousarray(gpu_acc, dtype=np.uint8),
+                             None if gpu_anchor is None else _f64(gpu_anchor),
+                             rel_tol, abs_tol, anchor_rel_tol, s_out, C.byref(rep))
+    return rc, rep.as_dict(), s_out
