@@ -1,0 +1,238 @@
+"""Thin ctypes binding of libamh.so (C ABI in include/amh.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP kernels of
+libamh.so.  PyTorch provides device memory and the stream.  There is no CPU
+fallback: if the library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamh.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "AMH_OK", -1: "AMH_E_INVAL", -2: "AMH_E_NOMEM", -3: "AMH_E_DEVICE",
+          -4: "AMH_E_NUMERIC", -5: "AMH_E_UNSUPPORTED", -6: "AMH_E_BUSY"}
+
+
+class AmhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class AmhConfig(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32), ("n_chains", C.c_int32), ("n_bins", C.c_int32), ("window_d", C.c_int32),
+        ("d_min", C.c_double), ("bin_w", C.c_double), ("global_every", C.c_int32),
+        ("anchor_every", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
+        ("total_sweeps", C.c_int64), ("seed", C.c_uint64), ("chain_offset", C.c_uint32),
+        ("chains_per_group", C.c_int32), ("waves_per_group", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libamh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2211_03193_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    sig = {
+        "amh_init": [C.POINTER(AmhConfig), _P, _P, _P, C.POINTER(_P)],
+        "amh_sweep": [_P, C.c_int64],
+        "amh_energy": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
+        "amh_conformation": [_P, C.c_int32, C.c_int32, _P, _P],
+        "amh_get_state": [_P, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)],
+        "amh_set_state": [_P, _P, _P, _P, _P, _P, C.c_int64],
+        "amh_set_target": [_P, C.c_double],
+        "amh_set_trace": [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, C.c_int64, _P, C.c_int64],
+        "amh_poll": [_P],
+        "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                     C.POINTER(C.c_int64)],
+        "amh_grad": [_P, _P, C.c_int32, _P, _P],
+        "amh_submit": [_P, _P, C.POINTER(C.c_uint64)],
+        "amh_destroy": [_P],
+        "amh_philox": [_P, C.c_int64, C.c_uint64, _P, _P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
+    L.amh_last_error.argtypes = []
+    L.amh_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise AmhError(status, lib().amh_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_config(w, **over) -> AmhConfig:
+    """amh_config from a workload description (synthetic.Workload or any object
+    with the same attribute names)."""
+    cfg = AmhConfig(L=w.L, n_chains=w.n_chains, n_bins=w.n_bins, window_d=w.window_d,
+                    d_min=w.d_min, bin_w=w.bin_w, global_every=w.global_every,
+                    anchor_every=w.anchor_period, sigma=math.radians(w.sigma_deg), T0=w.T0,
+                    T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed, chain_offset=0,
+                    chains_per_group=0, waves_per_group=0, reserved=0)
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """A sampler on the current GPU: C chains of one protein (amh_init .. amh_destroy)."""
+
+    def __init__(self, cfg: AmhConfig, y: torch.Tensor, s0: torch.Tensor | None = None,
+                 stream=None):
+        if not y.is_cuda or y.dtype != torch.float32 or not y.is_contiguous():
+            raise ValueError("y must be a contiguous float32 CUDA tensor [P][n_bins]")
+        P = cfg.L * (cfg.L - 1) // 2
+        if tuple(y.shape) != (P, cfg.n_bins):
+            raise ValueError(f"y has shape {tuple(y.shape)}, expected {(P, cfg.n_bins)}")
+        if s0 is not None:
+            if not s0.is_cuda or s0.dtype != torch.float64 or not s0.is_contiguous():
+                raise ValueError("s0 must be a contiguous float64 CUDA tensor [C][2L]")
+            if tuple(s0.shape) != (cfg.n_chains, 2 * cfg.L):
+                raise ValueError(f"s0 has shape {tuple(s0.shape)}, expected {(cfg.n_chains, 2 * cfg.L)}")
+        self.cfg = cfg
+        self.device = y.device
+        self._stream_obj = stream if stream is not None else torch.cuda.current_stream(y.device)
+        self._h = C.c_void_p()
+        self._trace_keep = None
+        check(lib().amh_init(C.byref(cfg), _ptr(y), _ptr(s0), _stream(self._stream_obj),
+                             C.byref(self._h)))
+
+    @property
+    def L(self) -> int:
+        return self.cfg.L
+
+    @property
+    def C(self) -> int:
+        return self.cfg.n_chains
+
+    def sweep(self, n: int) -> None:
+        check(lib().amh_sweep(self._h, n))
+
+    def energy(self, s: torch.Tensor | None = None, which: int = 0, want_s: bool = False,
+               want_cb: bool = False):
+        B = self.C if s is None else s.shape[0]
+        if s is not None and (s.dtype != torch.float64 or not s.is_contiguous() or s.shape[1] != 2 * self.L):
+            raise ValueError("s must be a contiguous float64 tensor [B][2L]")
+        V = torch.empty(B, dtype=torch.float64, device=self.device)
+        so = torch.empty(B, 2 * self.L, dtype=torch.float64, device=self.device) if want_s else None
+        cb = torch.empty(B, self.L, 3, dtype=torch.float32, device=self.device) if want_cb else None
+        check(lib().amh_energy(self._h, _ptr(s), B, which, _ptr(V), _ptr(so), _ptr(cb)))
+        return V, so, cb
+
+    def get_state(self) -> dict:
+        n, Cc, L = 2 * self.L, self.C, self.L
+        d = self.device
+        st = {"s": torch.empty(Cc, n, dtype=torch.float64, device=d),
+              "s_best": torch.empty(Cc, n, dtype=torch.float64, device=d),
+              "v": torch.empty(Cc, 2, dtype=torch.float64, device=d),
+              "counters": torch.empty(Cc, 4, dtype=torch.int64, device=d),
+              "atoms": torch.empty(Cc, L, 4, 4, dtype=torch.float32, device=d)}
+        t = C.c_int64()
+        check(lib().amh_get_state(self._h, _ptr(st["s"]), _ptr(st["s_best"]), _ptr(st["v"]),
+                                  _ptr(st["counters"]), _ptr(st["atoms"]), C.byref(t)))
+        st["t"] = t.value
+        return st
+
+    def set_state(self, st: dict, with_atoms: bool = True) -> None:
+        check(lib().amh_set_state(self._h, _ptr(st.get("s")), _ptr(st.get("s_best")),
+                                  _ptr(st.get("v")), _ptr(st.get("counters")),
+                                  _ptr(st.get("atoms")) if with_atoms else None, int(st["t"])))
+
+    def set_target(self, target: float) -> None:
+        check(lib().amh_set_target(self._h, target))
+
+    def set_trace(self, chain_ids, n_sweeps: int) -> dict:
+        """Trace every proposal of the given chains (<= 4) over the next n_sweeps sweeps."""
+        ids = list(chain_ids)
+        n = len(ids)
+        cap = n_sweeps * 2 * self.L
+        A = self.cfg.anchor_every
+        t = self.info()["t"]
+        acap = (t + n_sweeps) // A - t // A
+        d = self.device
+        rows = max(n, 1)
+        tr = {"dE": torch.zeros(rows, cap, dtype=torch.float64, device=d),
+              "delta": torch.zeros(rows, cap, dtype=torch.float64, device=d),
+              "acc": torch.zeros(rows, cap, dtype=torch.uint8, device=d),
+              "anchor": torch.zeros(rows, max(acap, 1), dtype=torch.float64, device=d),
+              "chains": ids, "t0": t, "n_sweeps": n_sweeps}
+        arr = (C.c_int32 * 4)(*(ids + [-1] * (4 - n)))
+        self._trace_keep = tr
+        check(lib().amh_set_trace(self._h, n, arr, _ptr(tr["dE"]), _ptr(tr["delta"]),
+                                  _ptr(tr["acc"]), cap, _ptr(tr["anchor"]), acap))
+        return tr
+
+    def clear_trace(self) -> None:
+        check(lib().amh_set_trace(self._h, 0, None, None, None, None, 0, None, 0))
+        self._trace_keep = None
+
+    def poll(self) -> None:
+        check(lib().amh_poll(self._h))
+
+    def info(self) -> dict:
+        g, w, l = C.c_int32(), C.c_int32(), C.c_int32()
+        t = C.c_int64()
+        check(lib().amh_info(self._h, C.byref(g), C.byref(w), C.byref(l), C.byref(t)))
+        return {"chains_per_group": g.value, "waves_per_group": w.value, "lds_bytes": l.value,
+                "t": t.value}
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().amh_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def conformation(s: torch.Tensor, stream=None) -> torch.Tensor:
+    """G(s): atoms [B][L][4][3] float32 (N, CA, C, C-beta) of s [B][2L] float64."""
+    if not s.is_cuda or s.dtype != torch.float64 or not s.is_contiguous() or s.dim() != 2:
+        raise ValueError("s must be a contiguous float64 CUDA tensor [B][2L]")
+    B, n = s.shape
+    out = torch.empty(B, n // 2, 4, 3, dtype=torch.float32, device=s.device)
+    check(lib().amh_conformation(_ptr(s), B, n // 2, _ptr(out), _stream(stream)))
+    return out
+
+
+def philox(ctr: torch.Tensor, key: int, stream=None) -> torch.Tensor:
+    """Philox4x32-10 blocks of counters ctr [n][4] (int32 view of uint32) with a 64-bit key."""
+    if not ctr.is_cuda or ctr.dtype != torch.int32 or not ctr.is_contiguous():
+        raise ValueError("ctr must be a contiguous int32 CUDA tensor [n][4]")
+    out = torch.empty_like(ctr)
+    check(lib().amh_philox(_ptr(ctr), ctr.shape[0], key, _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,192 @@
+// amh_device.h -- device-side building blocks of the AMH sampler for gfx950.
+//
+// Philox4x32-10 (Salmon et al., SC'11), the Box-Muller proposal increment, the
+// NeRF placement step in float64, Rodrigues rotation about a bond axis in float32,
+// and the Catmull-Rom distogram spline in float32 (hot loop) and float64 (anchors).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amh {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+
+// Ideal backbone geometry (Angstrom, degrees): N-CA, CA-C, C-N, CA-CB bonds; the
+// N-CA-C, CA-C-N, C-N-CA and N-CA-CB angles; omega and the C-N-CA-CB torsion.
+constexpr double kBondNCA = 1.458, kBondCAC = 1.525, kBondCN = 1.329, kBondCACB = 1.53;
+constexpr double kAngNCAC = 111.2, kAngCACN = 116.2, kAngCNCA = 121.7, kAngNCACB = 110.5;
+constexpr double kTorOmega = 180.0, kTorCB = -122.5;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of two 32x32->64 multiplies and xors, the key bumped
+// by the golden-ratio Weyl constants between rounds.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double open_unit(uint32_t x) {
+  return ((double)x + 0.5) * (1.0 / 4294967296.0);
+}
+
+// Randoms of proposal k of sweep t of chain `chain`: counter (k, t, chain, 0).
+struct Draw { double delta, log_u; float cd, sd; };
+
+__device__ __forceinline__ Draw proposal_draw(uint32_t k, uint32_t t, uint32_t chain, uint32_t k0,
+                                              uint32_t k1, double sigma) {
+  U4 x = philox10(U4{k, t, chain, 0u}, k0, k1);
+  double u0 = open_unit(x.x), u1 = open_unit(x.y), u2 = open_unit(x.z);
+  Draw d;
+  d.delta = sigma * sqrt(-2.0 * log(u0)) * cos(kTwoPi * u1);
+  d.log_u = log(u2);
+  double sd, cd;
+  sincos(d.delta, &sd, &cd);
+  d.cd = (float)cd;
+  d.sd = (float)sd;
+  return d;
+}
+
+__device__ __forceinline__ double wrap_angle(double a) {
+  if (a > kPi) a -= kTwoPi;
+  else if (a <= -kPi) a += kTwoPi;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Rotation by angle (c, s) about the unit axis through `a` along B - A.
+struct Rot {
+  float r[9];
+  float a[3];
+  float pad;
+  double log_u;  // acceptance log-uniform of the proposal the rotation belongs to
+};
+
+__device__ __forceinline__ void make_rot(float ax, float ay, float az, float bx, float by,
+                                         float bz, float c, float s, Rot& R) {
+  float ux = bx - ax, uy = by - ay, uz = bz - az;
+  float inv = rsqrtf(ux * ux + uy * uy + uz * uz);
+  ux *= inv; uy *= inv; uz *= inv;
+  const float t = 1.0f - c;
+  R.r[0] = c + t * ux * ux;      R.r[1] = t * ux * uy - s * uz; R.r[2] = t * ux * uz + s * uy;
+  R.r[3] = t * uy * ux + s * uz; R.r[4] = c + t * uy * uy;      R.r[5] = t * uy * uz - s * ux;
+  R.r[6] = t * uz * ux - s * uy; R.r[7] = t * uz * uy + s * ux; R.r[8] = c + t * uz * uz;
+  R.a[0] = ax; R.a[1] = ay; R.a[2] = az;
+}
+
+__device__ __forceinline__ float4 apply_rot(const Rot& R, float4 x) {
+  const float vx = x.x - R.a[0], vy = x.y - R.a[1], vz = x.z - R.a[2];
+  float4 o;
+  o.x = R.a[0] + R.r[0] * vx + R.r[1] * vy + R.r[2] * vz;
+  o.y = R.a[1] + R.r[3] * vx + R.r[4] * vy + R.r[5] * vz;
+  o.z = R.a[2] + R.r[6] * vx + R.r[7] * vy + R.r[8] * vz;
+  o.w = 0.0f;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Catmull-Rom spline of -ln p over the bin centres.  A padded row holds
+// [y1, y0, y1, ..., y_{nb-1}, y_{nb-2}, pad...]: entry b+1 is y_b and the two
+// mirrored ghosts sit at both ends, so the 4-tap stencil of interval b is
+// row[b .. b+3] for every b in [0, nb-2].
+struct Spline32 {
+  float inv_w;  // 1 / bin width
+  float off;    // (d_min + w/2) / w
+  float tmax;   // nb - 1
+};
+
+__device__ __forceinline__ float spline32(const float* __restrict__ row, float d, const Spline32& S) {
+  float t = fmaf(d, S.inv_w, -S.off);
+  t = fminf(fmaxf(t, 0.0f), S.tmax);
+  const float bf = fminf(floorf(t), S.tmax - 1.0f);
+  const float f = t - bf;
+  const float* q = row + (int)bf;
+  const float y0 = q[0], y1 = q[1], y2 = q[2], y3 = q[3];
+  const float a1 = y2 - y0;
+  const float a2 = 2.0f * y0 - 5.0f * y1 + 4.0f * y2 - y3;
+  const float a3 = 3.0f * (y1 - y2) + y3 - y0;
+  return fmaf(0.5f * f, fmaf(f, fmaf(f, a3, a2), a1), y1);
+}
+
+__device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,
+                                           double d_min, double w) {
+  const double t = (d - (d_min + 0.5 * w)) / w;
+  if (t <= 0.0) return (double)row[1];
+  if (t >= (double)(nb - 1)) return (double)row[nb];
+  const int b = (int)floor(t);
+  const double f = t - (double)b;
+  const double q0 = row[b], q1 = row[b + 1], q2 = row[b + 2], q3 = row[b + 3];
+  const double a0 = 2.0 * q1;
+  const double a1 = -q0 + q2;
+  const double a2 = 2.0 * q0 - 5.0 * q1 + 4.0 * q2 - q3;
+  const double a3 = -q0 + 3.0 * q1 - 3.0 * q2 + q3;
+  return 0.5 * (a0 + a1 * f + a2 * f * f + a3 * f * f * f);
+}
+
+// Packed row of the pair i < j.
+__device__ __forceinline__ int pair_row(int i, int j, int L) {
+  return i * L - ((i * (i + 1)) >> 1) + (j - i - 1);
+}
+
+// ---------------------------------------------------------------------------
+// NeRF placement in float64 (Parsons et al. 2005): D from A, B, C with bond l,
+// angle BCD (cos ct, sin st) and dihedral ABCD (cos cc, sin sc).
+__device__ __forceinline__ void nerf_place(const double* A, const double* B, const double* C,
+                                           double l, double ct, double st, double cc, double sc,
+                                           double* D) {
+  double bx = C[0] - B[0], by = C[1] - B[1], bz = C[2] - B[2];
+  double ib = 1.0 / sqrt(bx * bx + by * by + bz * bz);
+  bx *= ib; by *= ib; bz *= ib;
+  const double ax = B[0] - A[0], ay = B[1] - A[1], az = B[2] - A[2];
+  double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  double in = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+  nx *= in; ny *= in; nz *= in;
+  const double mx = ny * bz - nz * by, my = nz * bx - nx * bz, mz = nx * by - ny * bx;
+  const double d0 = -l * ct, d1 = l * st * cc, d2 = l * st * sc;
+  D[0] = C[0] + bx * d0 + mx * d1 + nx * d2;
+  D[1] = C[1] + by * d0 + my * d1 + ny * d2;
+  D[2] = C[2] + bz * d0 + mz * d1 + nz * d2;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Neumaier step: add x into (s, c).
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+}  // namespace amh

@@ -1,0 +1,75 @@
+// amh_kernels.h -- kernel parameter blocks and launch entry points shared by the
+// kernels (amh_kernels.hip) and the C ABI (amh_api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace amh {
+
+// bits of the device error word
+constexpr unsigned int kErrTable = 1u;   // non-finite distogram entry
+constexpr unsigned int kErrEnergy = 2u;  // non-finite energy or energy change
+
+struct SweepParams {
+  // distogram table, padded rows
+  const float* table;
+  int stride, nb;
+  float inv_w, off, tmax;
+  double d_min, bin_w;
+  // run
+  int L, C, half_window, global_every, anchor_every;
+  double sigma, T0, T1;
+  int64_t S, t0, n_sweeps;
+  uint32_t key0, key1, chain_offset;
+  double target;
+  // chain state
+  double* s;          // [C][2L]
+  double* s_best;     // [C][2L]
+  float4* atoms;      // [C][L][4]  N, CA, C, CB
+  double* v;          // [C][2]     V at last anchor, best V
+  int64_t* counters;  // [C][4]
+  unsigned int* err;
+  // trace
+  int n_trace;
+  int trace_chain[4];
+  double* tr_dE;
+  double* tr_delta;
+  uint8_t* tr_acc;
+  int64_t trace_cap, trace_t0;
+  double* tr_anchor;
+  int64_t trace_anchor_cap, trace_anchor0;
+};
+
+struct ConfParams {
+  int L;
+  const double* s_in;   // [B][2L] or null (extended chain)
+  // energy (optional: table == null skips it)
+  const float* table;
+  int stride, nb;
+  double d_min, bin_w;
+  double* V_out;        // [B]
+  double* s_out;        // [B][2L]
+  float* cb_out;        // [B][L][3]
+  float* atoms_out;     // [B][L][4][3]
+  float4* atoms4_out;   // [B][L][4]
+  // context initialisation (optional)
+  double* v_state;      // [B][2]
+  int64_t* counters;    // [B][4]
+  double* s_best;       // [B][2L]
+  unsigned int* err;
+};
+
+size_t sweep_lds_bytes(int G, int L, int W);
+inline size_t conf_lds_bytes(int L, int W) {
+  return 8 * (2 * (size_t)L + 3 * (size_t)L + 2 * (size_t)W + 2) + 16 * 4 * (size_t)L + 32;
+}
+
+__global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, float* out,
+                              unsigned int* err);
+__global__ void conf_energy_kernel(ConfParams P);
+__global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
+template <int G>
+__global__ void sweep_kernel(SweepParams P);
+
+}  // namespace amh
