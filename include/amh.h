@@ -96,16 +96,16 @@ amh_status amh_conformation(const double* s_dev, int32_t B, int32_t L, float* at
 /* Checkpoint / resume.  amh_get_state copies the context state out (any pointer may
  * be NULL): s [C][2L], s_best [C][2L], v [C][2] = (V at last anchor, best V),
  * counters [C][4] = (local accepts, global accepts, sweeps to target or -1,
- * anchors), atoms [C][L][4][4] float32 (N, CA, C, C-beta; 4th component 0) and the
+ * anchors), atoms [C][L][4][3] float64 (N, CA, C, C-beta) and the
  * host sweep counter *t_out.  amh_set_state loads it back; with atoms_dev given,
  * continuing from a restored state reproduces the uninterrupted run bit for bit;
  * with atoms_dev NULL the coordinates are rebuilt from s (exact at anchor sweeps,
  * where the sampler rebuilds them too). */
 amh_status amh_get_state(amh_ctx* ctx, double* s_dev, double* s_best_dev, double* v_dev,
-                         int64_t* counters_dev, float* atoms_dev, int64_t* t_out);
+                         int64_t* counters_dev, double* atoms_dev, int64_t* t_out);
 amh_status amh_set_state(amh_ctx* ctx, const double* s_dev, const double* s_best_dev,
                          const double* v_dev, const int64_t* counters_dev,
-                         const float* atoms_dev, int64_t t);
+                         const double* atoms_dev, int64_t t);
 
 /* Time-to-target: the first anchor with V <= target records its sweep count in
  * counters[c][2] (default target: -infinity, never reached). */

@@ -157,7 +157,7 @@ class Context:
               "s_best": torch.empty(Cc, n, dtype=torch.float64, device=d),
               "v": torch.empty(Cc, 2, dtype=torch.float64, device=d),
               "counters": torch.empty(Cc, 4, dtype=torch.int64, device=d),
-              "atoms": torch.empty(Cc, L, 4, 4, dtype=torch.float32, device=d)}
+              "atoms": torch.empty(Cc, L, 4, 3, dtype=torch.float64, device=d)}
         t = C.c_int64()
         check(lib().amh_get_state(self._h, _ptr(st["s"]), _ptr(st["s_best"]), _ptr(st["v"]),
                                   _ptr(st["counters"]), _ptr(st["atoms"]), C.byref(t)))

@@ -44,10 +44,11 @@ struct amh_ctx {
   amh_config cfg{};
   hipStream_t stream = nullptr;
   float* table = nullptr;
+  float* ydev = nullptr;
   int stride = 0;
   double* s = nullptr;
   double* s_best = nullptr;
-  float4* atoms = nullptr;
+  double* atoms = nullptr;   // [C][L][4][3]
   double* v = nullptr;
   int64_t* counters = nullptr;
   unsigned int* err = nullptr;
@@ -110,7 +111,7 @@ amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
 
 void free_ctx(amh_ctx* x) {
   if (!x) return;
-  (void)hipFree(x->table); (void)hipFree(x->s); (void)hipFree(x->s_best); (void)hipFree(x->atoms);
+  (void)hipFree(x->table); (void)hipFree(x->ydev); (void)hipFree(x->s); (void)hipFree(x->s_best); (void)hipFree(x->atoms);
   (void)hipFree(x->v); (void)hipFree(x->counters); (void)hipFree(x->err);
   delete x;
 }
@@ -175,9 +176,10 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   const int64_t P = (int64_t)L * (L - 1) / 2;
   x->stride = row_stride(cfg->n_bins);
   if ((st = dev_alloc(&x->table, (size_t)P * x->stride)) != AMH_OK ||
+      (st = dev_alloc(&x->ydev, (size_t)P * x->stride)) != AMH_OK ||
       (st = dev_alloc(&x->s, (size_t)C * n)) != AMH_OK ||
       (st = dev_alloc(&x->s_best, (size_t)C * n)) != AMH_OK ||
-      (st = dev_alloc(&x->atoms, (size_t)C * L * 4)) != AMH_OK ||
+      (st = dev_alloc(&x->atoms, (size_t)C * L * 12)) != AMH_OK ||
       (st = dev_alloc(&x->v, (size_t)C * 2)) != AMH_OK ||
       (st = dev_alloc(&x->counters, (size_t)C * 4)) != AMH_OK ||
       (st = dev_alloc(&x->err, 1)) != AMH_OK) {
@@ -190,7 +192,7 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
     int blocks = (int)((work + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(amh::ingest_kernel, dim3(blocks), dim3(256), 0, x->stream, y_dev, P,
-                       cfg->n_bins, x->stride, x->table, x->err);
+                       cfg->n_bins, x->stride, x->table, x->ydev, x->err);
     e = hipGetLastError();
   }
   if (e == hipSuccess && s0_dev)
@@ -202,7 +204,7 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   amh::ConfParams cp = conf_base(x);
   cp.s_in = s0_dev ? x->s : nullptr;
   cp.s_out = s0_dev ? nullptr : x->s;
-  cp.atoms4_out = x->atoms;
+  cp.atoms64_out = x->atoms;
   cp.v_state = x->v;
   cp.counters = x->counters;
   cp.s_best = x->s_best;
@@ -228,11 +230,16 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
   const amh_config& c = x->cfg;
   amh::SweepParams P{};
   P.table = x->table;
+  P.ydev = x->ydev;
   P.stride = x->stride;
   P.nb = c.n_bins;
   P.inv_w = (float)(1.0 / c.bin_w);
   P.off = (float)((c.d_min + 0.5 * c.bin_w) / c.bin_w);
   P.tmax = (float)(c.n_bins - 1);
+  {
+    const double dfar = c.d_min + c.bin_w * (c.n_bins - 0.5);   // last knot
+    P.d2far = (float)(dfar * dfar);
+  }
   P.d_min = c.d_min;
   P.bin_w = c.bin_w;
   P.L = c.L;
@@ -319,7 +326,7 @@ amh_status amh_conformation(const double* s_dev, int32_t B, int32_t L, float* at
 }
 
 amh_status amh_get_state(amh_ctx* x, double* s_dev, double* s_best_dev, double* v_dev,
-                         int64_t* counters_dev, float* atoms_dev, int64_t* t_out) {
+                         int64_t* counters_dev, double* atoms_dev, int64_t* t_out) {
   if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
   const size_t C = x->cfg.n_chains, n = 2 * (size_t)x->cfg.L;
   const auto D2D = hipMemcpyDeviceToDevice;
@@ -327,13 +334,13 @@ amh_status amh_get_state(amh_ctx* x, double* s_dev, double* s_best_dev, double* 
   if (s_best_dev) HIP_OK(hipMemcpyAsync(s_best_dev, x->s_best, sizeof(double) * C * n, D2D, x->stream));
   if (v_dev) HIP_OK(hipMemcpyAsync(v_dev, x->v, sizeof(double) * C * 2, D2D, x->stream));
   if (counters_dev) HIP_OK(hipMemcpyAsync(counters_dev, x->counters, sizeof(int64_t) * C * 4, D2D, x->stream));
-  if (atoms_dev) HIP_OK(hipMemcpyAsync(atoms_dev, x->atoms, sizeof(float4) * C * x->cfg.L * 4, D2D, x->stream));
+  if (atoms_dev) HIP_OK(hipMemcpyAsync(atoms_dev, x->atoms, sizeof(double) * C * x->cfg.L * 12, D2D, x->stream));
   if (t_out) *t_out = x->t;
   return AMH_OK;
 }
 
 amh_status amh_set_state(amh_ctx* x, const double* s_dev, const double* s_best_dev,
-                         const double* v_dev, const int64_t* counters_dev, const float* atoms_dev,
+                         const double* v_dev, const int64_t* counters_dev, const double* atoms_dev,
                          int64_t t) {
   if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
   if (t < 0 || t > x->cfg.total_sweeps) return fail(AMH_E_INVAL, "t=%lld out of range", (long long)t);
@@ -344,12 +351,12 @@ amh_status amh_set_state(amh_ctx* x, const double* s_dev, const double* s_best_d
   if (v_dev) HIP_OK(hipMemcpyAsync(x->v, v_dev, sizeof(double) * C * 2, D2D, x->stream));
   if (counters_dev) HIP_OK(hipMemcpyAsync(x->counters, counters_dev, sizeof(int64_t) * C * 4, D2D, x->stream));
   if (atoms_dev) {
-    HIP_OK(hipMemcpyAsync(x->atoms, atoms_dev, sizeof(float4) * C * x->cfg.L * 4, D2D, x->stream));
+    HIP_OK(hipMemcpyAsync(x->atoms, atoms_dev, sizeof(double) * C * x->cfg.L * 12, D2D, x->stream));
   } else if (s_dev) {
     amh::ConfParams P{};
     P.L = x->cfg.L;
     P.s_in = x->s;
-    P.atoms4_out = x->atoms;
+    P.atoms64_out = x->atoms;
     amh_status st = launch_conf(P, (int)C, x->stream);
     if (st != AMH_OK) return st;
   }

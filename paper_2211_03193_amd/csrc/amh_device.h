@@ -1,7 +1,7 @@
 // amh_device.h -- device-side building blocks of the AMH sampler for gfx950.
 //
 // Philox4x32-10 (Salmon et al., SC'11), the Box-Muller proposal increment, the
-// NeRF placement step in float64, Rodrigues rotation about a bond axis in float32,
+// NeRF placement step and Rodrigues rotation about a bond axis in float64,
 // and the Catmull-Rom distogram spline in float32 (hot loop) and float64 (anchors).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -40,7 +40,7 @@ __device__ __forceinline__ double open_unit(uint32_t x) {
 }
 
 // Randoms of proposal k of sweep t of chain `chain`: counter (k, t, chain, 0).
-struct Draw { double delta, log_u; float cd, sd; };
+struct Draw { double delta, log_u, cd, sd; };
 
 __device__ __forceinline__ Draw proposal_draw(uint32_t k, uint32_t t, uint32_t chain, uint32_t k0,
                                               uint32_t k1, double sigma) {
@@ -49,10 +49,7 @@ __device__ __forceinline__ Draw proposal_draw(uint32_t k, uint32_t t, uint32_t c
   Draw d;
   d.delta = sigma * sqrt(-2.0 * log(u0)) * cos(kTwoPi * u1);
   d.log_u = log(u2);
-  double sd, cd;
-  sincos(d.delta, &sd, &cd);
-  d.cd = (float)cd;
-  d.sd = (float)sd;
+  sincos(d.delta, &d.sd, &d.cd);
   return d;
 }
 
@@ -63,34 +60,46 @@ __device__ __forceinline__ double wrap_angle(double a) {
 }
 
 // ---------------------------------------------------------------------------
-// Rotation by angle (c, s) about the unit axis through `a` along B - A.
+// Float64 coordinates: atom a of residue r at x[(4 r + a) * 3 .. +2] (N, CA, C, CB).
+struct D3 { double x, y, z; };
+
+__device__ __forceinline__ D3 ld3(const double* p) { return D3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ void st3(double* p, D3 v) { p[0] = v.x; p[1] = v.y; p[2] = v.z; }
+
+// Rotation by angle (c, s) about the unit axis through `a` along B - A (float64).
 struct Rot {
-  float r[9];
-  float a[3];
-  float pad;
+  double r[9];
+  double a[3];
   double log_u;  // acceptance log-uniform of the proposal the rotation belongs to
 };
 
-__device__ __forceinline__ void make_rot(float ax, float ay, float az, float bx, float by,
-                                         float bz, float c, float s, Rot& R) {
-  float ux = bx - ax, uy = by - ay, uz = bz - az;
-  float inv = rsqrtf(ux * ux + uy * uy + uz * uz);
+__device__ __forceinline__ void make_rot(D3 A, D3 B, double c, double s, Rot& R) {
+  double ux = B.x - A.x, uy = B.y - A.y, uz = B.z - A.z;
+  const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
   ux *= inv; uy *= inv; uz *= inv;
-  const float t = 1.0f - c;
+  const double t = 1.0 - c;
   R.r[0] = c + t * ux * ux;      R.r[1] = t * ux * uy - s * uz; R.r[2] = t * ux * uz + s * uy;
   R.r[3] = t * uy * ux + s * uz; R.r[4] = c + t * uy * uy;      R.r[5] = t * uy * uz - s * ux;
   R.r[6] = t * uz * ux - s * uy; R.r[7] = t * uz * uy + s * ux; R.r[8] = c + t * uz * uz;
-  R.a[0] = ax; R.a[1] = ay; R.a[2] = az;
+  R.a[0] = A.x; R.a[1] = A.y; R.a[2] = A.z;
 }
 
-__device__ __forceinline__ float4 apply_rot(const Rot& R, float4 x) {
-  const float vx = x.x - R.a[0], vy = x.y - R.a[1], vz = x.z - R.a[2];
-  float4 o;
-  o.x = R.a[0] + R.r[0] * vx + R.r[1] * vy + R.r[2] * vz;
-  o.y = R.a[1] + R.r[3] * vx + R.r[4] * vy + R.r[5] * vz;
-  o.z = R.a[2] + R.r[6] * vx + R.r[7] * vy + R.r[8] * vz;
-  o.w = 0.0f;
-  return o;
+// R (x - a): the rotated position relative to the pivot point.
+__device__ __forceinline__ D3 rot_rel(const Rot& R, D3 x) {
+  const double vx = x.x - R.a[0], vy = x.y - R.a[1], vz = x.z - R.a[2];
+  return D3{R.r[0] * vx + R.r[1] * vy + R.r[2] * vz, R.r[3] * vx + R.r[4] * vy + R.r[5] * vz,
+            R.r[6] * vx + R.r[7] * vy + R.r[8] * vz};
+}
+
+__device__ __forceinline__ D3 apply_rot(const Rot& R, D3 x) {
+  const D3 v = rot_rel(R, x);
+  return D3{R.a[0] + v.x, R.a[1] + v.y, R.a[2] + v.z};
+}
+
+// float32 squared distance of two float64 points (difference taken in float64).
+__device__ __forceinline__ float dist2_64(D3 a, D3 b) {
+  const float dx = (float)(b.x - a.x), dy = (float)(b.y - a.y), dz = (float)(b.z - a.z);
+  return dx * dx + dy * dy + dz * dz;
 }
 
 // ---------------------------------------------------------------------------
@@ -115,6 +124,13 @@ __device__ __forceinline__ float spline32(const float* __restrict__ row, float d
   const float a2 = 2.0f * y0 - 5.0f * y1 + 4.0f * y2 - y3;
   const float a3 = 3.0f * (y1 - y2) + y3 - y0;
   return fmaf(0.5f * f, fmaf(f, fmaf(f, a3, a2), a1), y1);
+}
+
+// Pair energy minus the pair's no-contact value, from a row of the deviation table:
+// exactly zero beyond the last knot (squared distance d2far), where the spline is flat.
+__device__ __forceinline__ float edev32(const float* __restrict__ dev_row, float d2, const Spline32& S,
+                                        float d2far) {
+  return d2 < d2far ? spline32(dev_row, sqrtf(d2), S) : 0.0f;
 }
 
 __device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,

@@ -13,9 +13,10 @@ constexpr unsigned int kErrEnergy = 2u;  // non-finite energy or energy change
 
 struct SweepParams {
   // distogram table, padded rows
-  const float* table;
+  const float* table;     // padded -ln p rows (anchors)
+  const float* ydev;      // padded rows minus the no-contact value (sweeps)
   int stride, nb;
-  float inv_w, off, tmax;
+  float inv_w, off, tmax, d2far;
   double d_min, bin_w;
   // run
   int L, C, half_window, global_every, anchor_every;
@@ -26,7 +27,7 @@ struct SweepParams {
   // chain state
   double* s;          // [C][2L]
   double* s_best;     // [C][2L]
-  float4* atoms;      // [C][L][4]  N, CA, C, CB
+  double* atoms;      // [C][L][4][3] N, CA, C, CB (float64)
   double* v;          // [C][2]     V at last anchor, best V
   int64_t* counters;  // [C][4]
   unsigned int* err;
@@ -52,7 +53,7 @@ struct ConfParams {
   double* s_out;        // [B][2L]
   float* cb_out;        // [B][L][3]
   float* atoms_out;     // [B][L][4][3]
-  float4* atoms4_out;   // [B][L][4]
+  double* atoms64_out;  // [B][L][4][3]
   // context initialisation (optional)
   double* v_state;      // [B][2]
   int64_t* counters;    // [B][4]
@@ -62,11 +63,11 @@ struct ConfParams {
 
 size_t sweep_lds_bytes(int G, int L, int W);
 inline size_t conf_lds_bytes(int L, int W) {
-  return 8 * (2 * (size_t)L + 3 * (size_t)L + 2 * (size_t)W + 2) + 16 * 4 * (size_t)L + 32;
+  return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)W + 2) + 32;
 }
 
 __global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, float* out,
-                              unsigned int* err);
+                              float* dev, unsigned int* err);
 __global__ void conf_energy_kernel(ConfParams P);
 __global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
 template <int G>

@@ -14,13 +14,23 @@
 //   * localized sweeps are run by one wavefront per chain with no workgroup
 //     barrier; residues beyond the window are brought up to date lazily with one
 //     accumulated rigid transform (float64) when they enter the window;
+//   * pair energies are handled as deviations from the pair's no-contact value
+//     (a second copy of the table with that value subtracted), which are exactly
+//     zero beyond the last knot: a pair farther apart than 20.25 A costs a
+//     distance and a compare, no table access;
 //   * global proposals use every wavefront of the workgroup; dE of pivot p is
-//     S_new(p) - R(p), where R(p), the energy of the pair rectangle i < p <= j of
-//     the current conformation, is carried from proposal to proposal (the new
-//     rectangle sum on accept, an O(L) row/column update when p advances), so
-//     each global proposal evaluates one spline per changed pair instead of two;
+//     D_new(p) - D(p), where D(p), the deviation energy of the pair rectangle
+//     i < p <= j of the current conformation, is carried from proposal to
+//     proposal (the new rectangle sum on accept, an O(L) row/column update when
+//     p advances), so each global proposal evaluates one spline per changed near
+//     pair instead of two;
 //   * the proposal randoms come from Philox4x32-10 at counter (k, t, chain, 0),
 //     the same stream the oracle replays, drawn 64 proposals at a time, one per lane;
+//   * the master coordinates (N, CA, C, C-beta) live in LDS in float64 and are
+//     rotated in float64; the O(L^2) pair loop reads float32 C-beta positions taken
+//     relative to the pivot point, rounded once per proposal, so float32 never
+//     accumulates error in the state (an extended 300-residue chain spans ~1000 A,
+//     where float32 resolves only ~6e-5 A);
 //   * after every anchor sweep the coordinates are rebuilt from the float64
 //     torsions by NeRF and V is re-anchored in float64 with Neumaier summation.
 #include <hip/hip_runtime.h>
@@ -35,9 +45,10 @@ constexpr double kDeg = kPi / 180.0;
 
 // ---------------------------------------------------------------------------
 // Table ingest: repack [P][nb] rows into padded rows [y1, y0..y_{nb-1}, y_{nb-2}, 0...]
-// and flag non-finite entries.
+// (`out`) and the same rows minus the row's no-contact value y_{nb-1} (`dev`, rounded
+// once from float64), and flag non-finite entries.
 __global__ void ingest_kernel(const float* __restrict__ y, int64_t P, int nb, int stride,
-                              float* __restrict__ out, unsigned int* err) {
+                              float* __restrict__ out, float* __restrict__ dev, unsigned int* err) {
   const int64_t n = P * (int64_t)stride;
   bool bad = false;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
@@ -50,6 +61,7 @@ __global__ void ingest_kernel(const float* __restrict__ y, int64_t P, int nb, in
     else if (c == nb + 1) v = y[r * nb + (nb - 2)];
     if (c <= nb && !isfinite(v)) bad = true;
     out[e] = v;
+    dev[e] = c <= nb + 1 ? (float)((double)v - (double)y[r * nb + (nb - 1)]) : 0.0f;
   }
   if (bad) atomicOr(err, kErrTable);
 }
@@ -64,13 +76,16 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
   }
 }
 
+__device__ __forceinline__ double* atom(double* x64, int r, int a) { return x64 + (4 * r + a) * 3; }
+__device__ __forceinline__ const double* atom(const double* x64, int r, int a) {
+  return x64 + (4 * r + a) * 3;
+}
+
 // ---------------------------------------------------------------------------
-// Serial float64 NeRF of one chain, executed in lockstep by a whole wavefront
-// (all lanes hold the same values; the torsion cosines and sines are computed
-// 64 at a time, one per lane).  Writes float32 N/CA/C and C-beta and, if cb64 is
-// given, float64 C-beta.
-__device__ void nerf_chain(const double* __restrict__ s, int L, float4* __restrict__ bb,
-                           float4* __restrict__ cb, double* __restrict__ cb64, int lane) {
+// Serial float64 NeRF of one chain, executed in lockstep by a whole wavefront (all
+// lanes hold the same values; the torsion cosines and sines are computed 64 at a
+// time, one per lane).  Lane 0 writes the float64 atoms x64 [L][4][3].
+__device__ void nerf_chain(const double* __restrict__ s, int L, double* __restrict__ x64, int lane) {
   const double ct_cacn = cos(kAngCACN * kDeg), st_cacn = sin(kAngCACN * kDeg);
   const double ct_cnca = cos(kAngCNCA * kDeg), st_cnca = sin(kAngCNCA * kDeg);
   const double ct_ncac = cos(kAngNCAC * kDeg), st_ncac = sin(kAngNCAC * kDeg);
@@ -82,29 +97,20 @@ __device__ void nerf_chain(const double* __restrict__ s, int L, float4* __restri
   double C[3] = {kBondNCA - kBondCAC * ct_ncac, kBondCAC * st_ncac, 0.0};
   const int n = 2 * L;
   double cs = 1.0, sn = 0.0;
+  {
+    const double a = lane < n ? s[lane] : 0.0;
+    sincos(a, &sn, &cs);
+  }
   for (int c = 0; c < L; ++c) {
     if (c > 0) {
-      // torsions 2c-1 (psi_{c-1}) and 2c (phi_c)
-      const int m0 = 2 * c - 1;
-      double cpsi, spsi, cphi, sphi;
-      {
-        const int b = m0 & ~63;
-        if (m0 == b || c == 1) {
-          const int m = b + lane;
-          const double a = m < n ? s[m] : 0.0;
-          sincos(a, &sn, &cs);
-        }
-        cpsi = readlane_d(cs, m0 - b);
-        spsi = readlane_d(sn, m0 - b);
-        const int m1 = m0 + 1;
-        if ((m1 & 63) == 0) {
-          const int m = m1 + lane;
-          const double a = m < n ? s[m] : 0.0;
-          sincos(a, &sn, &cs);
-        }
-        cphi = readlane_d(cs, m1 & 63);
-        sphi = readlane_d(sn, m1 & 63);
+      const int m0 = 2 * c - 1, m1 = 2 * c;   // psi_{c-1}, phi_c
+      const double cpsi = readlane_d(cs, m0 & 63), spsi = readlane_d(sn, m0 & 63);
+      if ((m1 & 63) == 0) {
+        const int m = m1 + lane;
+        const double a = m < n ? s[m] : 0.0;
+        sincos(a, &sn, &cs);
       }
+      const double cphi = readlane_d(cs, m1 & 63), sphi = readlane_d(sn, m1 & 63);
       double Nn[3], CAn[3], Cn[3];
       nerf_place(N, CA, C, kBondCN, ct_cacn, st_cacn, cpsi, spsi, Nn);
       nerf_place(CA, C, Nn, kBondNCA, ct_cnca, st_cnca, co, so, CAn);
@@ -115,63 +121,44 @@ __device__ void nerf_chain(const double* __restrict__ s, int L, float4* __restri
     double B[3];
     nerf_place(C, N, CA, kBondCACB, ct_ncacb, st_ncacb, ccb, scb, B);
     if (lane == 0) {
-      bb[3 * c + 0] = make_float4((float)N[0], (float)N[1], (float)N[2], 0.0f);
-      bb[3 * c + 1] = make_float4((float)CA[0], (float)CA[1], (float)CA[2], 0.0f);
-      bb[3 * c + 2] = make_float4((float)C[0], (float)C[1], (float)C[2], 0.0f);
-      cb[c] = make_float4((float)B[0], (float)B[1], (float)B[2], 0.0f);
-      if (cb64) { cb64[3 * c] = B[0]; cb64[3 * c + 1] = B[1]; cb64[3 * c + 2] = B[2]; }
+      double* o = atom(x64, c, 0);
+      o[0] = N[0]; o[1] = N[1]; o[2] = N[2];
+      o[3] = CA[0]; o[4] = CA[1]; o[5] = CA[2];
+      o[6] = C[0]; o[7] = C[1]; o[8] = C[2];
+      o[9] = B[0]; o[10] = B[1]; o[11] = B[2];
     }
   }
 }
 
-// Float64 energy sum over all pairs i < j of `nchain` conformations held as
-// float64 C-beta in LDS (cb64[g] = base + g * 3L).  Each thread accumulates a
-// Neumaier pair (sum, compensation) per chain; the wavefronts' partials are
-// combined in a fixed order by wave 0.  red64 needs 2 * nwaves * nchain doubles.
-template <int G>
-__device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min,
-                         double w, int L, const double* __restrict__ cb64, int nchain,
-                         double* red64, double* V_out /*[G] in LDS*/) {
+// Float64 energy V = sum_{i<j} E_ij(|CB_i - CB_j|) of one conformation (C-beta read
+// from x64), each thread accumulating a Neumaier pair; the wavefronts' partials
+// are combined in a fixed order.  red64 holds 2 * nwaves doubles; the result is
+// written to *V_out by thread 0 and is visible after the final barrier.
+__device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min, double w,
+                         int L, const double* __restrict__ x64, double* red64, double* V_out) {
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
-  double sum[G], cmp[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) { sum[g] = 0.0; cmp[g] = 0.0; }
-  // walk the strict upper triangle row by row with stride T
+  double sum = 0.0, cmp = 0.0;
   int i = 0, j = 1 + tid;
+  while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
   while (i < L - 1) {
-    if (j < L) {
-      const float* row = table + (size_t)pair_row(i, j, L) * stride;
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        if (g < nchain) {
-          const double* p = cb64 + (size_t)g * 3 * L;
-          const double dx = p[3 * j] - p[3 * i], dy = p[3 * j + 1] - p[3 * i + 1],
-                       dz = p[3 * j + 2] - p[3 * i + 2];
-          neumaier_add(sum[g], cmp[g], spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w));
-        }
-      }
-      j += T;
-    }
+    const float* row = table + (size_t)pair_row(i, j, L) * stride;
+    const double* a = atom(x64, i, 3);
+    const double* b = atom(x64, j, 3);
+    const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    neumaier_add(sum, cmp, spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w));
+    j += T;
     while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
   }
-  // combine: within a wave (fixed butterfly order), then across waves in wave order
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    double s = sum[g], c = cmp[g];
-    for (int o = 32; o > 0; o >>= 1) {
-      const double so = __shfl_down(s, o, 64), co = __shfl_down(c, o, 64);
-      if (lane < o) { neumaier_add(s, c, so); c += co; }
-    }
-    if (lane == 0) { red64[2 * (wave * G + g)] = s; red64[2 * (wave * G + g) + 1] = c; }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double so = __shfl_down(sum, o, 64), co = __shfl_down(cmp, o, 64);
+    if (lane < o) { neumaier_add(sum, cmp, so); cmp += co; }
   }
+  if (lane == 0) { red64[2 * wave] = sum; red64[2 * wave + 1] = cmp; }
   __syncthreads();
-  if (tid < G && tid < nchain) {
+  if (tid == 0) {
     double s = 0.0, c = 0.0;
-    for (int v = 0; v < W; ++v) {
-      neumaier_add(s, c, red64[2 * (v * G + tid)]);
-      c += red64[2 * (v * G + tid) + 1];
-    }
-    V_out[tid] = s + c;
+    for (int v = 0; v < W; ++v) { neumaier_add(s, c, red64[2 * v]); c += red64[2 * v + 1]; }
+    *V_out = s + c;
   }
   __syncthreads();
 }
@@ -180,46 +167,33 @@ __device__ void energy64(const float* __restrict__ table, int stride, int nb, do
 // Conformation / energy kernel: one workgroup per conformation.
 __global__ void conf_energy_kernel(ConfParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int L = P.L, tid = threadIdx.x, lane = tid & 63;
+  const int L = P.L, tid = threadIdx.x, lane = tid & 63, W = blockDim.x >> 6;
   const int b = blockIdx.x;
-  double* s = reinterpret_cast<double*>(lds);                 // [2L]
-  double* cb64 = s + 2 * L;                                   // [3L]
-  double* red64 = cb64 + 3 * L;                               // [2 * W]
-  double* Vs = red64 + 2 * (blockDim.x >> 6);                 // [1]
-  float4* bb = reinterpret_cast<float4*>((reinterpret_cast<uintptr_t>(Vs + 2) + 15) & ~uintptr_t(15));  // [3L]
-  float4* cb = bb + 3 * L;                                    // [L]
+  double* s = reinterpret_cast<double*>(lds);   // [2L]
+  double* x64 = s + 2 * L;                      // [12L]
+  double* red64 = x64 + 12 * L;                 // [2W]
+  double* Vs = red64 + 2 * W;                   // [1]
   const double* src = P.s_in ? P.s_in + (size_t)b * 2 * L : nullptr;
   for (int m = tid; m < 2 * L; m += blockDim.x) s[m] = src ? src[m] : kPi;
   __syncthreads();
-  if (tid < 64) nerf_chain(s, L, bb, cb, cb64, lane);
+  if (tid < 64) nerf_chain(s, L, x64, lane);
   __syncthreads();
   if (P.atoms_out) {
     float* o = P.atoms_out + (size_t)b * L * 12;
-    for (int e = tid; e < L * 12; e += blockDim.x) {
-      const int r = e / 12, a = (e % 12) / 3, x = e % 3;
-      const float4 v = a < 3 ? bb[3 * r + a] : cb[r];
-      o[e] = x == 0 ? v.x : (x == 1 ? v.y : v.z);
-    }
+    for (int e = tid; e < L * 12; e += blockDim.x) o[e] = (float)x64[e];
   }
-  if (P.atoms4_out) {
-    float4* o = P.atoms4_out + (size_t)b * L * 4;
-    for (int e = tid; e < L * 4; e += blockDim.x) {
-      const int r = e >> 2, a = e & 3;
-      o[e] = a < 3 ? bb[3 * r + a] : cb[r];
-    }
+  if (P.atoms64_out) {
+    double* o = P.atoms64_out + (size_t)b * L * 12;
+    for (int e = tid; e < L * 12; e += blockDim.x) o[e] = x64[e];
   }
   if (P.cb_out) {
     float* o = P.cb_out + (size_t)b * L * 3;
-    for (int e = tid; e < L * 3; e += blockDim.x) {
-      const float4 v = cb[e / 3];
-      const int x = e % 3;
-      o[e] = x == 0 ? v.x : (x == 1 ? v.y : v.z);
-    }
+    for (int e = tid; e < L * 3; e += blockDim.x) o[e] = (float)atom(x64, e / 3, 3)[e % 3];
   }
   if (P.s_out)
     for (int m = tid; m < 2 * L; m += blockDim.x) P.s_out[(size_t)b * 2 * L + m] = s[m];
   if (P.table) {
-    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, cb64, 1, red64, Vs);
+    energy64(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, x64, red64, Vs);
     if (tid == 0) {
       const double V = Vs[0];
       if (!isfinite(V)) atomicOr(P.err, kErrEnergy);
@@ -236,65 +210,45 @@ __global__ void conf_energy_kernel(ConfParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// The sweep kernel.
-// LDS layout of a sweep workgroup: per chain (stride `per` bytes) the current
-// C-beta [L], the trial C-beta [L] (which also holds 3L float64 C-beta at anchors),
-// N/CA/C [3L] and the torsions [2L]; then the shared rotation slots and partials.
-__host__ __device__ inline int off_bb(int L) { return 16 * L + ((24 * L + 15) & ~15); }
-__host__ __device__ inline int lds_per_chain(int L) { return off_bb(L) + 64 * L; }
-
+// LDS layout of a sweep workgroup: per chain (stride 128 L bytes) the float64
+// atoms [L][4][3], the float32 pivot-relative C-beta work array [L] and the
+// torsions [2L]; then the rotation slots of the current and next proposal per
+// chain, the wavefront partials and the anchor scratch.
 struct Lds {
   unsigned char* base;
-  int L, per, G;
-  unsigned char* tail;
-  __device__ float4* cb(int g) const { return reinterpret_cast<float4*>(base + (size_t)g * per); }
-  __device__ float4* cbt(int g) const { return reinterpret_cast<float4*>(base + (size_t)g * per + 16 * L); }
-  __device__ double* cb64(int g) const { return reinterpret_cast<double*>(cbt(g)); }
-  __device__ float4* bb(int g) const { return reinterpret_cast<float4*>(base + (size_t)g * per + off_bb(L)); }
-  __device__ double* s(int g) const { return reinterpret_cast<double*>(base + (size_t)g * per + off_bb(L) + 48 * L); }
-  __device__ Rot* par() const { return reinterpret_cast<Rot*>(tail); }
-  __device__ double* red() const { return reinterpret_cast<double*>(tail + sizeof(Rot) * 2 * G); }
+  int L, G;
+  __device__ size_t per() const { return 128 * (size_t)L; }
+  __device__ double* x64(int g) const { return reinterpret_cast<double*>(base + g * per()); }
+  __device__ float4* w32(int g) const { return reinterpret_cast<float4*>(base + g * per() + 96 * (size_t)L); }
+  __device__ double* s(int g) const { return reinterpret_cast<double*>(base + g * per() + 112 * (size_t)L); }
+  __device__ Rot* par() const { return reinterpret_cast<Rot*>(base + G * per()); }
+  __device__ double* red() const { return reinterpret_cast<double*>(par() + 2 * G); }
   __device__ double* red64(int W) const { return red() + 2 * W * G; }
-  __device__ double* Vtmp(int W) const { return red64(W) + 2 * W * G; }
+  __device__ double* Vtmp(int W) const { return red64(W) + 2 * W; }
 };
 
-__device__ __forceinline__ Lds carve(unsigned char* base, int L, int G) {
-  Lds d;
-  d.base = base;
-  d.L = L;
-  d.G = G;
-  d.per = lds_per_chain(L);
-  d.tail = base + (size_t)G * d.per;
-  return d;
-}
-
 size_t sweep_lds_bytes(int G, int L, int W) {
-  return (size_t)G * lds_per_chain(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G * 2 +
+  return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
          8 * (size_t)G + 64;
 }
 
-// Rotation of the proposal k of one chain (the owner wavefront computes it from
-// the pivot bond of residue k/2 and the drawn increment).
-__device__ __forceinline__ void axis_atoms(const float4* bb, int k, float4& A, float4& B) {
+__device__ __forceinline__ void axis_atoms(const double* x64, int k, D3& A, D3& B) {
   const int c = k >> 1;
-  if (k & 1) { A = bb[3 * c + 1]; B = bb[3 * c + 2]; }   // psi_c: CA_c -> C_c
-  else { A = bb[3 * c + 0]; B = bb[3 * c + 1]; }         // phi_c: N_c -> CA_c
+  if (k & 1) { A = ld3(atom(x64, c, 1)); B = ld3(atom(x64, c, 2)); }  // psi_c: CA_c -> C_c
+  else { A = ld3(atom(x64, c, 0)); B = ld3(atom(x64, c, 1)); }        // phi_c: N_c -> CA_c
 }
 
 struct Batch {  // proposal randoms of 64 consecutive proposals, one per lane
-  double delta, log_u;
-  float cd, sd;
+  double delta, log_u, cd, sd;
 };
 
 __device__ __forceinline__ Batch fill_batch(const SweepParams& P, int kb, uint32_t t,
                                             uint32_t chain, int lane) {
   const int k = kb + lane;
-  Batch b;
+  Batch b{0.0, 0.0, 1.0, 0.0};
   if (k < 2 * P.L) {
     const Draw d = proposal_draw((uint32_t)k, t, chain, P.key0, P.key1, P.sigma);
     b.delta = d.delta; b.log_u = d.log_u; b.cd = d.cd; b.sd = d.sd;
-  } else {
-    b.delta = 0.0; b.log_u = 0.0; b.cd = 1.0f; b.sd = 0.0f;
   }
   return b;
 }
@@ -321,8 +275,7 @@ __device__ __forceinline__ void trace_step(const SweepParams& P, int slot, int64
 __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain, int64_t t,
                             double beta, int lane, int slot, int64_t& n_acc) {
   const int L = P.L, n = 2 * L, h = P.half_window;
-  float4* __restrict__ cb = S.cb(g);
-  float4* __restrict__ bb = S.bb(g);
+  double* __restrict__ x64 = S.x64(g);
   double* __restrict__ s = S.s(g);
   const Spline32 sp{P.inv_w, P.off, P.tmax};
   // accumulated rigid transform x -> A x + b of the residues that have not yet
@@ -339,12 +292,11 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
     while (entered < hi) {
       ++entered;
       if (moved && lane < 4) {
-        const float4 x = lane < 3 ? bb[3 * entered + lane] : cb[entered];
-        const double X = x.x, Y = x.y, Z = x.z;
-        const float4 o = make_float4((float)(A[0] * X + A[1] * Y + A[2] * Z + tb[0]),
-                                     (float)(A[3] * X + A[4] * Y + A[5] * Z + tb[1]),
-                                     (float)(A[6] * X + A[7] * Y + A[8] * Z + tb[2]), 0.0f);
-        if (lane < 3) bb[3 * entered + lane] = o; else cb[entered] = o;
+        double* q = atom(x64, entered, lane);
+        const double X = q[0], Y = q[1], Z = q[2];
+        q[0] = A[0] * X + A[1] * Y + A[2] * Z + tb[0];
+        q[1] = A[3] * X + A[4] * Y + A[5] * Z + tb[1];
+        q[2] = A[6] * X + A[7] * Y + A[8] * Z + tb[2];
       }
       wave_sync();
     }
@@ -356,29 +308,25 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
     double dE = 0.0;
     Rot R;
     if (live) {
-      float4 a, b;
-      axis_atoms(bb, k, a, b);
-      make_rot(a.x, a.y, a.z, b.x, b.y, b.z, readlane_f(bt.cd, kl), readlane_f(bt.sd, kl), R);
+      D3 a, b;
+      axis_atoms(x64, k, a, b);
+      make_rot(a, b, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
       if (npair > 0) {
         double part = 0.0;
         for (int x = lane; x < npair; x += 64) {
           const int ii = lo + x / nM, j = p + x % nM;
-          const float4 xi = cb[ii], xj = cb[j];
-          const float4 xt = apply_rot(R, xj);
-          const float* row = P.table + (size_t)pair_row(ii, j, L) * P.stride;
-          const float dx0 = xj.x - xi.x, dy0 = xj.y - xi.y, dz0 = xj.z - xi.z;
-          const float dx1 = xt.x - xi.x, dy1 = xt.y - xi.y, dz1 = xt.z - xi.z;
-          const float e0 = spline32(row, sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0), sp);
-          const float e1 = spline32(row, sqrtf(dx1 * dx1 + dy1 * dy1 + dz1 * dz1), sp);
+          const D3 xi = ld3(atom(x64, ii, 3)), xj = ld3(atom(x64, j, 3));
+          const D3 xt = apply_rot(R, xj);
+          const float* row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
+          const float e0 = edev32(row, dist2_64(xi, xj), sp, P.d2far);
+          const float e1 = edev32(row, dist2_64(xi, xt), sp, P.d2far);
           part += (double)e1 - (double)e0;
         }
         dE = wave_sum(part);
       }
     }
     const int acc = (dE <= 0.0) || (log_u < -beta * dE);
-    if (lane == 0) {
-      if (!isfinite(dE)) atomicOr(P.err, kErrEnergy);
-    }
+    if (lane == 0 && !isfinite(dE)) atomicOr(P.err, kErrEnergy);
     trace_step(P, lane == 0 ? slot : -1, t, k, dE, delta, acc);
     if (acc) {
       if (lane == 0) s[k] = wrap_angle(s[k] + delta);
@@ -389,8 +337,8 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
         for (int x = lane; x < 4 * nres; x += 64) {
           const int r = p + (x >> 2), at = x & 3;
           if (!(k & 1) && r == c && at < 2) continue;   // phi_c leaves N_c and CA_c in place
-          if (at < 3) bb[3 * r + at] = apply_rot(R, bb[3 * r + at]);
-          else cb[r] = apply_rot(R, cb[r]);
+          double* q = atom(x64, r, at);
+          st3(q, apply_rot(R, ld3(q)));
         }
         // compose the pending transform: x -> R (x - a) + a after (A, b)
         double nA[9], nb[3];
@@ -398,10 +346,9 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
         for (int r = 0; r < 3; ++r) {
 #pragma unroll
           for (int q = 0; q < 3; ++q)
-            nA[3 * r + q] = (double)R.r[3 * r] * A[q] + (double)R.r[3 * r + 1] * A[3 + q] +
-                            (double)R.r[3 * r + 2] * A[6 + q];
-          nb[r] = (double)R.r[3 * r] * (tb[0] - R.a[0]) + (double)R.r[3 * r + 1] * (tb[1] - R.a[1]) +
-                  (double)R.r[3 * r + 2] * (tb[2] - R.a[2]) + (double)R.a[r];
+            nA[3 * r + q] = R.r[3 * r] * A[q] + R.r[3 * r + 1] * A[3 + q] + R.r[3 * r + 2] * A[6 + q];
+          nb[r] = R.r[3 * r] * (tb[0] - R.a[0]) + R.r[3 * r + 1] * (tb[1] - R.a[1]) +
+                  R.r[3 * r + 2] * (tb[2] - R.a[2]) + R.a[r];
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) A[q] = nA[q];
@@ -413,18 +360,16 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
   }
 }
 
-template <int G>
+// Anchor: rebuild every chain's coordinates from its float64 torsions (NeRF),
+// re-anchor V in float64 and update the best state and the time-to-target.
 __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int64_t t,
                        double* vbest_own, int64_t* ttt, int64_t* nanchor) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, L = P.L, W = blockDim.x >> 6;
   __syncthreads();
-  if (wave < nact) nerf_chain(S.s(wave), L, S.bb(wave), S.cb(wave), S.cb64(wave), lane);
+  if (wave < nact) nerf_chain(S.s(wave), L, S.x64(wave), lane);
   __syncthreads();
-#pragma unroll
-  for (int g = 0; g < G; ++g)
-    if (g < nact)
-      energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, S.cb64(g), 1, S.red64(W),
-                  S.Vtmp(W) + g);
+  for (int g = 0; g < nact; ++g)
+    energy64(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, S.x64(g), S.red64(W), S.Vtmp(W) + g);
   if (wave < nact) {
     const int g = wave, chain = c0 + g;
     const double v = S.Vtmp(W)[g];
@@ -457,14 +402,13 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
   const int L = P.L, n = 2 * L;
   const int c0 = blockIdx.x * G;
   const int nact = P.C - c0 < G ? P.C - c0 : G;
-  const Lds S = carve(lds, L, G);
+  const Lds S{lds, L, G};
   const Spline32 sp{P.inv_w, P.off, P.tmax};
 
   // load chain state
-  for (int e = tid; e < nact * L * 4; e += T) {
-    const int g = e / (4 * L), r = (e >> 2) % L, a = e & 3;
-    const float4 v = P.atoms[((size_t)(c0 + g) * L + r) * 4 + a];
-    if (a < 3) S.bb(g)[3 * r + a] = v; else S.cb(g)[r] = v;
+  for (int e = tid; e < nact * L * 12; e += T) {
+    const int g = e / (12 * L), q = e - g * 12 * L;
+    S.x64(g)[q] = P.atoms[(size_t)(c0 + g) * L * 12 + q];
   }
   for (int e = tid; e < nact * n; e += T) {
     const int g = e / n, m = e % n;
@@ -477,9 +421,9 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
   const int my_chain = c0 + wave;
   const int slot = owner ? trace_slot(P, my_chain) : -1;
   if (owner) {
-    ttt = P.counters[4 * my_chain + 2];
     acc_local = P.counters[4 * my_chain + 0];
     acc_global = P.counters[4 * my_chain + 1];
+    ttt = P.counters[4 * my_chain + 2];
     nanchor = P.counters[4 * my_chain + 3];
   }
   __syncthreads();
@@ -498,13 +442,13 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
 #pragma unroll
       for (int g = 0; g < G; ++g) Rp[g] = 0.0;
       Batch bt{};
-      float4 nA = make_float4(0, 0, 0, 0), nB = nA;   // owner: raw axis atoms of k+1
+      D3 nA{0, 0, 0}, nB{0, 0, 0};   // owner: pivot bond of proposal k+1
       if (owner) {
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
-        float4 a, b;
-        axis_atoms(S.bb(wave), 0, a, b);
+        D3 a, b;
+        axis_atoms(S.x64(wave), 0, a, b);
         Rot R;
-        make_rot(a.x, a.y, a.z, b.x, b.y, b.z, readlane_f(bt.cd, 0), readlane_f(bt.sd, 0), R);
+        make_rot(a, b, readlane_d(bt.cd, 0), readlane_d(bt.sd, 0), R);
         R.log_u = readlane_d(bt.log_u, 0);
         if (lane == 0) S.par()[wave] = R;
       }
@@ -512,15 +456,21 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
       for (int k = 0; k < n; ++k) {
         const int c = k >> 1, p = (k & 1) ? c + 1 : c, M = L - p;
         const Rot* pr = S.par() + (k & 1) * G;
-        // [B] trial positions of the moved C-beta
-        for (int e = tid; e < nact * M; e += T) {
-          const int g = e / M, j = p + (e - g * M);
-          S.cbt(g)[j] = apply_rot(pr[g], S.cb(g)[j]);
+        // [B] float32 C-beta relative to the pivot point: current below the pivot,
+        // rotated (trial) from the pivot on
+        for (int e = tid; e < nact * L; e += T) {
+          const int g = e / L, r = e - g * L;
+          const Rot& R = pr[g];
+          const D3 x = ld3(atom(S.x64(g), r, 3));
+          D3 v;
+          if (r < p) v = D3{x.x - R.a[0], x.y - R.a[1], x.z - R.a[2]};
+          else v = rot_rel(R, x);
+          S.w32(g)[r] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
         }
-        if (owner && k + 1 < n) axis_atoms(S.bb(wave), k + 1, nA, nB);
+        if (owner && k + 1 < n) axis_atoms(S.x64(wave), k + 1, nA, nB);
         __syncthreads();
-        // [C] rectangle i < p <= j with the trial positions, and (odd k) the row and
-        // column that move the rectangle from pivot p-1 to p, with the current ones
+        // [C] rectangle i < p <= j (trial), and for odd k the row and column that
+        // carry the rectangle energy from pivot p-1 to p (current conformation)
         double acc[G], tr[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) { acc[g] = 0.0; tr[g] = 0.0; }
@@ -530,13 +480,14 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
           const int di = T / M, dj = T - (T / M) * M;
           while (i < p) {
             const int j = p + jj;
-            const float* row = P.table + (size_t)pair_row(i, j, L) * P.stride;
+            const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               if (g < nact) {
-                const float4 xi = S.cb(g)[i], xj = S.cbt(g)[j];
+                const float4 xi = S.w32(g)[i], xj = S.w32(g)[j];
                 const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-                acc[g] += (double)spline32(row, sqrtf(dx * dx + dy * dy + dz * dz), sp);
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 < P.d2far) acc[g] += (double)spline32(row, sqrtf(d2), sp);
               }
             }
             jj += dj; i += di;
@@ -549,15 +500,12 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
             double sgn;
             if (x < p - 1) { i = x; j = p - 1; sgn = -1.0; }
             else { i = p - 1; j = p + (x - (p - 1)); sgn = 1.0; }
-            const float* row = P.table + (size_t)pair_row(i, j, L) * P.stride;
+            const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-              if (g < nact) {
-                const float4 xi = S.cb(g)[i], xj = S.cb(g)[j];
-                const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-                tr[g] += sgn * (double)spline32(row, sqrtf(dx * dx + dy * dy + dz * dz), sp);
-              }
-            }
+            for (int g = 0; g < G; ++g)
+              if (g < nact)
+                tr[g] += sgn * (double)edev32(row, dist2_64(ld3(atom(S.x64(g), i, 3)),
+                                                            ld3(atom(S.x64(g), j, 3))), sp, P.d2far);
           }
         }
 #pragma unroll
@@ -594,16 +542,16 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
           trace_step(P, lane == 0 ? slot : -1, t, k, dE_own, delta, a);
           acc_global += a;
         }
-        // [E] commit accepted moves
+        // [E] commit accepted moves: rotate (float64) every atom the torsion moves
         if (accmask) {
           const int per = 4 * M;
           for (int e = tid; e < nact * per; e += T) {
             const int g = e / per;
             if (!((accmask >> g) & 1)) continue;
             const int x = e - g * per, r = p + (x >> 2), at = x & 3;
-            if (at == 3) { S.cb(g)[r] = S.cbt(g)[r]; continue; }
             if (!(k & 1) && r == c && at < 2) continue;   // phi_c leaves N_c and CA_c in place
-            S.bb(g)[3 * r + at] = apply_rot(pr[g], S.bb(g)[3 * r + at]);
+            double* q = atom(S.x64(g), r, at);
+            st3(q, apply_rot(pr[g], ld3(q)));
           }
         }
         // owner: rotation of proposal k+1 from the post-commit pivot bond
@@ -616,21 +564,21 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
           }
           const int kl = kn & 63;
           Rot R;
-          make_rot(nA.x, nA.y, nA.z, nB.x, nB.y, nB.z, readlane_f(bt.cd, kl), readlane_f(bt.sd, kl), R);
+          make_rot(nA, nB, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
           R.log_u = readlane_d(bt.log_u, kl);
           if (lane == 0) S.par()[(kn & 1) * G + wave] = R;
         }
         __syncthreads();
       }
     }
-    if (((t + 1) % P.anchor_every) == 0) anchor<G>(P, S, c0, nact, t, &vbest_own, &ttt, &nanchor);
+    if (((t + 1) % P.anchor_every) == 0) anchor(P, S, c0, nact, t, &vbest_own, &ttt, &nanchor);
   }
 
   // store chain state
   __syncthreads();
-  for (int e = tid; e < nact * L * 4; e += T) {
-    const int g = e / (4 * L), r = (e >> 2) % L, a = e & 3;
-    P.atoms[((size_t)(c0 + g) * L + r) * 4 + a] = a < 3 ? S.bb(g)[3 * r + a] : S.cb(g)[r];
+  for (int e = tid; e < nact * L * 12; e += T) {
+    const int g = e / (12 * L), q = e - g * 12 * L;
+    P.atoms[(size_t)(c0 + g) * L * 12 + q] = S.x64(g)[q];
   }
   for (int e = tid; e < nact * n; e += T) {
     const int g = e / n, m = e % n;
