@@ -176,7 +176,7 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   const int64_t P = (int64_t)L * (L - 1) / 2;
   x->stride = row_stride(cfg->n_bins);
   if ((st = dev_alloc(&x->table, (size_t)P * x->stride)) != AMH_OK ||
-      (st = dev_alloc(&x->ydev, (size_t)P * x->stride)) != AMH_OK ||
+      (st = dev_alloc(&x->ydev, (size_t)(P + 1) * x->stride)) != AMH_OK ||
       (st = dev_alloc(&x->s, (size_t)C * n)) != AMH_OK ||
       (st = dev_alloc(&x->s_best, (size_t)C * n)) != AMH_OK ||
       (st = dev_alloc(&x->atoms, (size_t)C * L * 12)) != AMH_OK ||
@@ -187,6 +187,8 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
     return st;
   }
   hipError_t e = hipMemsetAsync(x->err, 0, sizeof(unsigned int), x->stream);
+  if (e == hipSuccess)   // row P of the deviation table is the zero row
+    e = hipMemsetAsync(x->ydev + (size_t)P * x->stride, 0, sizeof(float) * x->stride, x->stream);
   if (e == hipSuccess) {
     const int64_t work = P * x->stride;
     int blocks = (int)((work + 255) / 256);
@@ -231,6 +233,7 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
   amh::SweepParams P{};
   P.table = x->table;
   P.ydev = x->ydev;
+  P.zrow = x->ydev + (size_t)c.L * (c.L - 1) / 2 * x->stride;
   P.stride = x->stride;
   P.nb = c.n_bins;
   P.inv_w = (float)(1.0 / c.bin_w);

@@ -84,6 +84,27 @@ __device__ __forceinline__ void make_rot(D3 A, D3 B, double c, double s, Rot& R)
   R.a[0] = A.x; R.a[1] = A.y; R.a[2] = A.z;
 }
 
+// Rotation by angle (c, s) about the unit axis u through the point A.
+__device__ __forceinline__ void make_rot_u(D3 A, D3 u, double c, double s, Rot& R) {
+  const double t = 1.0 - c;
+  R.r[0] = c + t * u.x * u.x;       R.r[1] = t * u.x * u.y - s * u.z; R.r[2] = t * u.x * u.z + s * u.y;
+  R.r[3] = t * u.y * u.x + s * u.z; R.r[4] = c + t * u.y * u.y;       R.r[5] = t * u.y * u.z - s * u.x;
+  R.r[6] = t * u.z * u.x - s * u.y; R.r[7] = t * u.z * u.y + s * u.x; R.r[8] = c + t * u.z * u.z;
+  R.a[0] = A.x; R.a[1] = A.y; R.a[2] = A.z;
+}
+
+__device__ __forceinline__ D3 unit(D3 A, D3 B) {
+  const double ux = B.x - A.x, uy = B.y - A.y, uz = B.z - A.z;
+  const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+  return D3{ux * inv, uy * inv, uz * inv};
+}
+
+// R v for a direction v (no translation).
+__device__ __forceinline__ D3 rot_dir(const Rot& R, D3 v) {
+  return D3{R.r[0] * v.x + R.r[1] * v.y + R.r[2] * v.z, R.r[3] * v.x + R.r[4] * v.y + R.r[5] * v.z,
+            R.r[6] * v.x + R.r[7] * v.y + R.r[8] * v.z};
+}
+
 // R (x - a): the rotated position relative to the pivot point.
 __device__ __forceinline__ D3 rot_rel(const Rot& R, D3 x) {
   const double vx = x.x - R.a[0], vy = x.y - R.a[1], vz = x.z - R.a[2];
@@ -113,24 +134,37 @@ struct Spline32 {
   float tmax;   // nb - 1
 };
 
-__device__ __forceinline__ float spline32(const float* __restrict__ row, float d, const Spline32& S) {
+// Knot interval b and fraction f of a distance: t = (d - first knot) / w clamped to
+// [0, nb-1], b = min(floor t, nb-2), f = t - b (f = 1 at the far clamp).
+__device__ __forceinline__ void spline_pos(float d, const Spline32& S, int& b, float& f) {
   float t = fmaf(d, S.inv_w, -S.off);
   t = fminf(fmaxf(t, 0.0f), S.tmax);
   const float bf = fminf(floorf(t), S.tmax - 1.0f);
-  const float f = t - bf;
-  const float* q = row + (int)bf;
-  const float y0 = q[0], y1 = q[1], y2 = q[2], y3 = q[3];
+  f = t - bf;
+  b = (int)bf;
+}
+
+// Uniform Catmull-Rom cubic through (y0, y1, y2, y3) at fraction f of [y1, y2].
+__device__ __forceinline__ float catmull_rom(float y0, float y1, float y2, float y3, float f) {
   const float a1 = y2 - y0;
   const float a2 = 2.0f * y0 - 5.0f * y1 + 4.0f * y2 - y3;
   const float a3 = 3.0f * (y1 - y2) + y3 - y0;
   return fmaf(0.5f * f, fmaf(f, fmaf(f, a3, a2), a1), y1);
 }
 
+__device__ __forceinline__ float spline32(const float* __restrict__ row, float d, const Spline32& S) {
+  int b;
+  float f;
+  spline_pos(d, S, b, f);
+  const float* q = row + b;
+  return catmull_rom(q[0], q[1], q[2], q[3], f);
+}
+
 // Pair energy minus the pair's no-contact value, from a row of the deviation table:
 // exactly zero beyond the last knot (squared distance d2far), where the spline is flat.
 __device__ __forceinline__ float edev32(const float* __restrict__ dev_row, float d2, const Spline32& S,
                                         float d2far) {
-  return d2 < d2far ? spline32(dev_row, sqrtf(d2), S) : 0.0f;
+  return d2 < d2far ? spline32(dev_row, __builtin_amdgcn_sqrtf(d2), S) : 0.0f;
 }
 
 __device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,
@@ -181,6 +215,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// DPP move of both halves of a double (row_mask, bank_mask all set, bound_ctrl on).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRor4 = 0x124;  // row_ror:4 (lane i of a row reads lane i-4 mod 16)
+constexpr int kDppRor8 = 0x128;  // row_ror:8
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -189,6 +235,16 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 
 __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum over the 64 lanes without LDS traffic: quad butterflies and row rotations by
+// DPP, then the four row totals in a fixed order; every lane gets the same value.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppRor4>(v);
+  v += dpp_d<kDppRor8>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Orders LDS traffic between the lanes of one wavefront.

@@ -15,6 +15,7 @@ struct SweepParams {
   // distogram table, padded rows
   const float* table;     // padded -ln p rows (anchors)
   const float* ydev;      // padded rows minus the no-contact value (sweeps)
+  const float* zrow;      // a padded row of zeros (read by pairs beyond the last knot)
   int stride, nb;
   float inv_w, off, tmax, d2far;
   double d_min, bin_w;

@@ -395,6 +395,14 @@ __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int
   __syncthreads();
 }
 
+// acc[g] += v for a lane-varying chain index g (kept in registers).
+template <int G>
+__device__ __forceinline__ void add_chain(double* acc, int g, double v) {
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+    if (q == g) acc[q] += v;
+}
+
 template <int G>
 __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
 #pragma unroll
       for (int g = 0; g < G; ++g) Rp[g] = 0.0;
       Batch bt{};
-      D3 nA{0, 0, 0}, nB{0, 0, 0};   // owner: pivot bond of proposal k+1
+      D3 nA{0, 0, 0}, nB{0, 0, 0}, nU{0, 0, 1};   // owner: pivot bond of proposal k+1
       if (owner) {
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
         D3 a, b;
@@ -456,18 +464,17 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
       for (int k = 0; k < n; ++k) {
         const int c = k >> 1, p = (k & 1) ? c + 1 : c, M = L - p;
         const Rot* pr = S.par() + (k & 1) * G;
-        // [B] float32 C-beta relative to the pivot point: current below the pivot,
-        // rotated (trial) from the pivot on
-        for (int e = tid; e < nact * L; e += T) {
-          const int g = e / L, r = e - g * L;
+        // [B] float32 C-beta of the fixed residues i < p relative to the pivot point
+        for (int e = tid; e < nact * p; e += T) {
+          const int g = e / p, r = e - g * p;
           const Rot& R = pr[g];
           const D3 x = ld3(atom(S.x64(g), r, 3));
-          D3 v;
-          if (r < p) v = D3{x.x - R.a[0], x.y - R.a[1], x.z - R.a[2]};
-          else v = rot_rel(R, x);
-          S.w32(g)[r] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
+          S.w32(g)[r] = make_float4((float)(x.x - R.a[0]), (float)(x.y - R.a[1]), (float)(x.z - R.a[2]), 0.0f);
         }
-        if (owner && k + 1 < n) axis_atoms(S.x64(wave), k + 1, nA, nB);
+        if (owner && k + 1 < n) {
+          axis_atoms(S.x64(wave), k + 1, nA, nB);
+          nU = unit(nA, nB);
+        }
         __syncthreads();
         // [C] rectangle i < p <= j (trial), and for odd k the row and column that
         // carry the rectangle energy from pivot p-1 to p (current conformation)
@@ -476,22 +483,59 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
         for (int g = 0; g < G; ++g) { acc[g] = 0.0; tr[g] = 0.0; }
         const int npairs = p * M;
         if (npairs > 0) {
-          int i = tid / M, jj = tid - (tid / M) * M;
-          const int di = T / M, dj = T - (T / M) * M;
-          while (i < p) {
-            const int j = p + jj;
-            const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
+          // each thread owns a column j (its trial C-beta in registers) and a segment
+          // of the rows i < p; the fixed C-beta x_i are read from LDS, the same i for
+          // the lanes of a segment.  Pairs farther apart than the last knot add 0.
+          const int nseg = M >= T ? 1 : T / M;
+          const int seglen = (p + nseg - 1) / nseg;
+          for (int item = tid; item < nseg * M; item += T) {
+            const int sgi = item / M, jj = item - sgi * M, j = p + jj;
+            const int ib = sgi * seglen, ie = ib + seglen < p ? ib + seglen : p;
+            float tx[G], ty[G], tz[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               if (g < nact) {
-                const float4 xi = S.w32(g)[i], xj = S.w32(g)[j];
-                const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-                const float d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 < P.d2far) acc[g] += (double)spline32(row, sqrtf(d2), sp);
+                const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
+                tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
+              } else {
+                tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
               }
             }
-            jj += dj; i += di;
-            if (jj >= M) { jj -= M; ++i; }
+            // a pair inside the last knot issues its table load and leaves it pending;
+            // it is consumed at the lane's next near pair or after the loop, so the
+            // wavefront does not wait on the load where it was issued
+            bool pend = false;
+            float4 py = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float pf = 0.0f;
+            int pg = 0;
+#pragma unroll 2
+            for (int i = ib; i < ie; ++i) {
+              float d2[G];
+              bool any = false;
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const float4 xi = S.w32(g)[i];
+                const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
+                d2[g] = dx * dx + dy * dy + dz * dz;
+                any |= d2[g] < P.d2far;
+              }
+              if (any) {
+                const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                  if (d2[g] < P.d2far) {
+                    if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
+                    int b;
+                    spline_pos(__builtin_amdgcn_sqrtf(d2[g]), sp, b, pf);
+                    const float* q = row + b;
+                    py = make_float4(q[0], q[1], q[2], q[3]);
+                    pg = g;
+                    pend = true;
+                  }
+                }
+              }
+            }
+            if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
           }
         }
         if (k & 1) {
@@ -511,19 +555,39 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           if (g < nact) {
-            const double a = wave_sum(acc[g]), b = wave_sum(tr[g]);
-            if (lane == 0) { S.red()[2 * (wave * G + g)] = a; S.red()[2 * (wave * G + g) + 1] = b; }
+            const double a = wave_sum_dpp(acc[g]), b = wave_sum_dpp(tr[g]);
+            if (lane == 0) { S.red()[(2 * g) * W + wave] = a; S.red()[(2 * g + 1) * W + wave] = b; }
           }
         }
         __syncthreads();
-        // [D] every wavefront takes the same decisions from the same partials
+        // [D] every wavefront takes the same decisions from the same partials: lane
+        // l < 2 W G holds partial (wave v, chain g, kind c) and the W waves of each
+        // (g, c) are summed in a fixed order
+        double part = lane < 2 * W * G ? S.red()[lane] : 0.0;
+        // sum each aligned group of W lanes: quad sums by DPP butterflies, then the
+        // quads of a group in lane order (W = 4 or 8; other W lane by lane)
+        if (W == 4 || W == 8) {
+          part += dpp_d<kDppXor1>(part);
+          part += dpp_d<kDppXor2>(part);
+        }
         unsigned int accmask = 0;
         double dE_own = 0.0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           if (g < nact) {
             double Snew = 0.0, Tr = 0.0;
-            for (int v = 0; v < W; ++v) { Snew += S.red()[2 * (v * G + g)]; Tr += S.red()[2 * (v * G + g) + 1]; }
+            if (W == 4) {
+              Snew = readlane_d(part, (2 * g) * W);
+              Tr = readlane_d(part, (2 * g + 1) * W);
+            } else if (W == 8) {
+              Snew = readlane_d(part, (2 * g) * W) + readlane_d(part, (2 * g) * W + 4);
+              Tr = readlane_d(part, (2 * g + 1) * W) + readlane_d(part, (2 * g + 1) * W + 4);
+            } else {
+              for (int v = 0; v < W; ++v) {
+                Snew += readlane_d(part, (2 * g) * W + v);
+                Tr += readlane_d(part, (2 * g + 1) * W + v);
+              }
+            }
             Rp[g] += Tr;
             const double dE = npairs > 0 ? Snew - Rp[g] : 0.0;
             const int a = (dE <= 0.0) || (pr[g].log_u < -beta * dE);
@@ -559,12 +623,15 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
           const int kn = k + 1;
           if ((kn & 63) == 0) bt = fill_batch(P, kn, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
           if ((accmask >> wave) & 1) {
-            if (k & 1) { nA = apply_rot(pr[wave], nA); nB = apply_rot(pr[wave], nB); }  // psi_c moved residue c+1
-            else nB = apply_rot(pr[wave], nB);                                         // phi_c moved C_c
+            // the accepted rotation turned the next pivot bond rigidly: psi_c moved
+            // residue c+1 (both atoms of the phi_{c+1} bond), phi_c moved C_c (the far
+            // atom of the psi_c bond, whose near atom CA_c lies on the phi_c axis)
+            if (k & 1) nA = apply_rot(pr[wave], nA);
+            nU = rot_dir(pr[wave], nU);
           }
           const int kl = kn & 63;
           Rot R;
-          make_rot(nA, nB, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
+          make_rot_u(nA, nU, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
           R.log_u = readlane_d(bt.log_u, kl);
           if (lane == 0) S.par()[(kn & 1) * G + wave] = R;
         }

@@ -127,6 +127,29 @@ def test_small_run_replays_and_is_layout_independent(G, W):
 
 _LAYOUT = {}
 
+WIDE = sy.Workload("wide", L=160, n_chains=5, total_sweeps=6, window_d=10, global_every=2,
+                   sigma_deg=12.0, T0=1.0, T1=0.2, seed=0x5EED02, protein_seed=8, noise_seed=9)
+
+
+@pytest.mark.parametrize("G,W", [(1, 1), (1, 4), (2, 8), (4, 8)])
+def test_wide_rectangles_use_every_wave(G, W):
+    """At L=160 the pair rectangle of a global proposal is split over all eight
+    wavefronts, so every wave's partial sums enter the decision."""
+    gu.say("wide run G", G, "W", W)
+    _, y = gu.protein(WIDE)
+    ctx = gu.context(WIDE, y, chains_per_group=G, waves_per_group=W)
+    chains = [0, 3, 4]
+    tr = gu.traced_run(ctx, chains, 6)
+    ctx.close()
+    if (G, W) == (1, 1):
+        _replay_all(WIDE, y, tr, chains)
+    key = (tr["dE"].tobytes(), tr["acc"].tobytes())
+    _WIDE.setdefault("ref", key)
+    assert key == _WIDE["ref"]
+
+
+_WIDE = {}
+
 
 def test_resume_is_bit_exact():
     gu.say("resume")
