@@ -404,6 +404,7 @@ amh_status amh_poll(amh_ctx* x) {
   unsigned int err = 0;
   amh_status st = read_err(x, &err);
   if (st != AMH_OK) return st;
+  if (err & amh::kErrStall) return fail(AMH_E_DEVICE, "a pipelined localized sweep exceeded its wait bound");
   if (err) return fail(AMH_E_NUMERIC, "non-finite %s", (err & amh::kErrTable) ? "table entry" : "energy");
   return AMH_OK;
 }

@@ -10,6 +10,7 @@ namespace amh {
 // bits of the device error word
 constexpr unsigned int kErrTable = 1u;   // non-finite distogram entry
 constexpr unsigned int kErrEnergy = 2u;  // non-finite energy or energy change
+constexpr unsigned int kErrStall = 4u;   // a pipelined localized sweep waited past its bound
 
 struct SweepParams {
   // distogram table, padded rows

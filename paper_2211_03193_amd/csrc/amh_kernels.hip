@@ -225,11 +225,16 @@ struct Lds {
   __device__ double* red() const { return reinterpret_cast<double*>(par() + 2 * G); }
   __device__ double* red64(int W) const { return red() + 2 * W * G; }
   __device__ double* Vtmp(int W) const { return red64(W) + 2 * W; }
+  // progress of the pipelined localized sweeps: [G][W] ints, then W int64 accept counts
+  __device__ int* prog(int W) const { return reinterpret_cast<int*>(Vtmp(W) + G); }
+  __device__ long long* nacc(int W) const {
+    return reinterpret_cast<long long*>(prog(W) + ((G * W + 1) & ~1));
+  }
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
   return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
-         8 * (size_t)G + 64;
+         8 * (size_t)G + 4 * (size_t)((G * W + 1) & ~1) + 8 * (size_t)W + 64;
 }
 
 __device__ __forceinline__ void axis_atoms(const double* x64, int k, D3& A, D3& B) {
@@ -272,8 +277,33 @@ __device__ __forceinline__ void trace_step(const SweepParams& P, int slot, int64
 }
 
 // Localized sweep of chain g by its owner wavefront (no workgroup barrier inside).
+// Pipelining: the m-th sweep of a block of consecutive localized sweeps publishes
+// m * 4096 + (proposals done) in `publish`; sweep m+1 waits on that counter so that
+// it runs proposal k' (residue c') only once sweep m stands at residue c'+2h+1 or
+// beyond.  A localized dE depends only on the geometry of its window, and a
+// rotation moves only residues downstream of its bond, so the two sweeps never
+// touch the same residues and the results equal those of running them in turn.
+struct Pipe {
+  const int* wait_on;   // progress counter of the previous sweep, or null
+  int* publish;         // this sweep's progress counter
+  int m;                // index of the sweep in its block
+};
+
+__device__ __forceinline__ bool wait_progress(const SweepParams& P, const int* ctr, int target,
+                                              bool& stalled) {
+  if (stalled) return false;
+  for (int spin = 0; spin < (1 << 24); ++spin) {
+    if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  stalled = true;   // bounded wait: flag the error and go on rather than hang
+  atomicOr(P.err, kErrStall);
+  return false;
+}
+
 __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain, int64_t t,
-                            double beta, int lane, int slot, int64_t& n_acc) {
+                            double beta, int lane, int slot, int64_t& n_acc, const Pipe& pipe,
+                            bool& stalled) {
   const int L = P.L, n = 2 * L, h = P.half_window;
   double* __restrict__ x64 = S.x64(g);
   double* __restrict__ s = S.s(g);
@@ -288,6 +318,10 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
     if ((k & 63) == 0) bt = fill_batch(P, k, (uint32_t)t, (uint32_t)(P.chain_offset + chain), lane);
     const int c = k >> 1, p = (k & 1) ? c + 1 : c;
     const int lo = c - h > 0 ? c - h : 0, hi = c + h < L - 1 ? c + h : L - 1;
+    if (pipe.wait_on) {
+      const int need = 2 * c + 4 * h + 2 < n ? 2 * c + 4 * h + 2 : n;
+      wait_progress(P, pipe.wait_on, (pipe.m - 1) * 4096 + need, stalled);
+    }
     // residues entering the window take the transform accumulated so far
     while (entered < hi) {
       ++entered;
@@ -357,6 +391,8 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
       }
     }
     wave_sync();
+    if (pipe.publish && lane == 0)
+      __hip_atomic_store(pipe.publish, pipe.m * 4096 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -436,14 +472,47 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
   }
   __syncthreads();
 
-  for (int64_t t = P.t0; t < P.t0 + P.n_sweeps; ++t) {
+  // the W/G wavefronts of chain g (waves g, g+G, ...) run the consecutive localized
+  // sweeps of a block in turn, pipelined
+  const int nstage = W / G, stage = wave / G, lg = wave - stage * G;
+  const bool stage_wave = stage < nstage && lg < nact;
+  const int lslot = stage_wave ? trace_slot(P, c0 + lg) : -1;
+  int64_t acc_local_stage = 0;
+  bool stalled = false;
+  const int64_t t_end = P.t0 + P.n_sweeps;
+  for (int64_t t = P.t0; t < t_end;) {
     const bool global = P.global_every > 0 && ((t + 1) % P.global_every) == 0;
     double T_t = P.T0;
     if (P.S > 1) T_t = P.T0 * pow(P.T1 / P.T0, (double)t / (double)(P.S - 1));
     const double beta = 1.0 / T_t;
     if (!global) {
-      if (owner) local_sweep(P, S, wave, my_chain, t, beta, lane, slot, acc_local);
+      // block [t, tb) of localized sweeps, ended by a global sweep, an anchor sweep,
+      // the end of the launch or 4096 sweeps
+      int64_t tb = t;
+      while (tb < t_end && tb - t < 4096 &&
+             !(P.global_every > 0 && ((tb + 1) % P.global_every) == 0)) {
+        ++tb;
+        if ((tb % P.anchor_every) == 0) break;
+      }
+      const int nblk = (int)(tb - t);
+      for (int e = tid; e < G * W; e += T) S.prog(W)[e] = 0;
       __syncthreads();
+      if (stage_wave) {
+        for (int m = stage; m < nblk; m += nstage) {
+          const int64_t tm = t + m;
+          double Tm = P.T0;
+          if (P.S > 1) Tm = P.T0 * pow(P.T1 / P.T0, (double)tm / (double)(P.S - 1));
+          Pipe pipe;
+          pipe.m = m;
+          pipe.publish = S.prog(W) + lg * W + stage;
+          pipe.wait_on = m > 0 ? S.prog(W) + lg * W + ((m - 1) % nstage) : nullptr;
+          local_sweep(P, S, lg, c0 + lg, tm, 1.0 / Tm, lane, lslot, acc_local_stage, pipe, stalled);
+        }
+      }
+      __syncthreads();
+      t = tb;
+      if ((t % P.anchor_every) == 0) anchor(P, S, c0, nact, t - 1, &vbest_own, &ttt, &nanchor);
+      continue;
     } else {
       // ---------------- global sweep, all wavefronts ----------------
       double Rp[G];
@@ -639,10 +708,16 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
       }
     }
     if (((t + 1) % P.anchor_every) == 0) anchor(P, S, c0, nact, t, &vbest_own, &ttt, &nanchor);
+    ++t;
   }
 
-  // store chain state
+  // store chain state; the localized-sweep accept counts of a chain's waves are summed
   __syncthreads();
+  if (lane == 0) S.nacc(W)[wave] = acc_local_stage;
+  __syncthreads();
+  if (owner)
+    for (int q = 1; q < nstage; ++q) acc_local_stage += S.nacc(W)[wave + q * G];
+  acc_local += acc_local_stage;
   for (int e = tid; e < nact * L * 12; e += T) {
     const int g = e / (12 * L), q = e - g * 12 * L;
     P.atoms[(size_t)(c0 + g) * L * 12 + q] = S.x64(g)[q];
