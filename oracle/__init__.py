@@ -25,6 +25,23 @@ class Cfg(C.Structure):
     ]
 
 
+class LbfgsOpts(C.Structure):
+    _fields_ = [
+        ("n_iter", C.c_int32), ("m", C.c_int32), ("nonmonotone", C.c_int32), ("max_ls", C.c_int32),
+        ("c1", C.c_double), ("shrink", C.c_double), ("gtol", C.c_double), ("step0", C.c_double),
+    ]
+
+
+def lbfgs_opts(n_iter=200, m=8, nonmonotone=5, max_ls=30, c1=1e-4, shrink=0.5, gtol=1e-6,
+               step0=0.1) -> LbfgsOpts:
+    return LbfgsOpts(n_iter=n_iter, m=m, nonmonotone=nonmonotone, max_ls=max_ls, c1=c1,
+                     shrink=shrink, gtol=gtol, step0=step0)
+
+
+FG_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                    C.POINTER(C.c_double))
+
+
 class ReplayReport(C.Structure):
     _fields_ = [
         ("n_steps", C.c_int64), ("n_forks", C.c_int64), ("n_de_fail", C.c_int64),
@@ -89,6 +106,13 @@ def lib():
                                  P(C.c_double)]
     L.oracle_delta_e.restype = C.c_double
     L.oracle_grad.argtypes = [P(Cfg), _D, _D, P(C.c_double), _D]
+    L.oracle_lbfgs_direction.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, C.c_double, _D]
+    L.oracle_lbfgs.argtypes = [C.c_int32, _D, P(LbfgsOpts), FG_FN, C.c_void_p, P(C.c_double),
+                               P(C.c_int32), _opt(_D)]
+    L.oracle_lbfgs.restype = C.c_int32
+    L.oracle_lbfgs_protein.argtypes = [P(Cfg), _D, _D, P(LbfgsOpts), P(C.c_double), P(C.c_int32),
+                                       _opt(_D)]
+    L.oracle_lbfgs_protein.restype = C.c_int32
     L.oracle_chain_init.argtypes = [P(Cfg), _D, C.c_int32, _D, _D, _D]
     L.oracle_run.argtypes = [P(Cfg), _D, C.c_int32, _opt(_U32), C.c_int64, C.c_int64, C.c_int32,
                              C.c_int32, _D, _D, _D, _I64, C.c_double, _opt(_D), _opt(_U8),
@@ -194,6 +218,48 @@ def grad(cfg: Cfg, y, s) -> tuple[float, np.ndarray]:
     V = C.c_double()
     lib().oracle_grad(C.byref(cfg), _f64(y), s, C.byref(V), g)
     return V.value, g
+
+
+def lbfgs_direction(S, Y, g, gamma: float) -> np.ndarray:
+    """-H g by the two-loop recursion over the rows of S, Y (oldest first)."""
+    g = _f64(g)
+    n = g.size
+    S = _f64(np.asarray(S).reshape(-1, n))
+    Y = _f64(np.asarray(Y).reshape(-1, n))
+    d = np.empty_like(g)
+    lib().oracle_lbfgs_direction(n, S.shape[0], S.ravel() if S.size else np.zeros(1), Y.ravel()
+                                 if Y.size else np.zeros(1), g, gamma, d)
+    return d
+
+
+def lbfgs(fg, x0, opts: LbfgsOpts | None = None):
+    """Minimise a Python callable fg(x) -> (f, g); returns (x, f, iters, status, f_trace)."""
+    opts = opts or lbfgs_opts()
+    x = _f64(x0).copy()
+    n = x.size
+
+    def _cb(_ctx, xp, fp, gp):
+        xv = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+        f, g = fg(xv)
+        fp[0] = float(f)
+        np.ctypeslib.as_array(gp, shape=(n,))[:] = g
+
+    cb = FG_FN(_cb)
+    f, it = C.c_double(), C.c_int32()
+    tr = np.full(opts.n_iter + 1, np.nan)
+    st = lib().oracle_lbfgs(n, x, C.byref(opts), cb, None, C.byref(f), C.byref(it), tr)
+    return x, f.value, it.value, st, tr[: it.value + 1]
+
+
+def lbfgs_protein(cfg: Cfg, y, s0, opts: LbfgsOpts | None = None):
+    """L-BFGS on V(s); returns (s wrapped, V, iters, status, f_trace)."""
+    opts = opts or lbfgs_opts()
+    s = _f64(s0).copy()
+    V, it = C.c_double(), C.c_int32()
+    tr = np.full(opts.n_iter + 1, np.nan)
+    st = lib().oracle_lbfgs_protein(C.byref(cfg), _f64(y), s, C.byref(opts), C.byref(V),
+                                    C.byref(it), tr)
+    return s, V.value, it.value, st, tr[: it.value + 1]
 
 
 class Chains:

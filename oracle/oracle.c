@@ -577,3 +577,144 @@ int32_t oracle_replay(const oracle_cfg *cfg, const double *y, uint32_t chain_id,
   free(s);
   return (rep->first_fail_step < 0) ? 0 : 1;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Limited-memory BFGS (Liu and Nocedal 1989) with a backtracking Armijo line
+ * search whose reference value is the largest of the last M accepted values
+ * (the nonmonotone rule of Grippo, Lampariello and Lucidi 1986; M = 1 is the
+ * monotone rule).  The paper pairs its sampler with a nonmonotone Armijo
+ * L-BFGS (Sec. 3, the L-BFGS columns of Fig. 3); the exact rules used here are
+ * the ones written below. */
+
+static double dotn(int32_t n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* Two-loop recursion: d = -H g, with H the inverse-Hessian approximation built
+ * from H0 = gamma I by the BFGS update with the k stored pairs, oldest first
+ * (pairs i = 0 .. k-1 in S[i*n..], Y[i*n..], oldest at 0). */
+void oracle_lbfgs_direction(int32_t n, int32_t k, const double *S, const double *Y,
+                            const double *g, double gamma, double *d) {
+  double *a = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
+  for (int32_t e = 0; e < n; ++e) d[e] = g[e];
+  for (int32_t i = k - 1; i >= 0; --i) {
+    const double *s = S + (size_t)i * n, *y = Y + (size_t)i * n;
+    double rho = 1.0 / dotn(n, y, s);
+    a[i] = rho * dotn(n, s, d);
+    for (int32_t e = 0; e < n; ++e) d[e] -= a[i] * y[e];
+  }
+  for (int32_t e = 0; e < n; ++e) d[e] *= gamma;
+  for (int32_t i = 0; i < k; ++i) {
+    const double *s = S + (size_t)i * n, *y = Y + (size_t)i * n;
+    double rho = 1.0 / dotn(n, y, s);
+    double b = rho * dotn(n, y, d);
+    for (int32_t e = 0; e < n; ++e) d[e] += (a[i] - b) * s[e];
+  }
+  for (int32_t e = 0; e < n; ++e) d[e] = -d[e];
+  free(a);
+}
+
+static double max_abs(int32_t n, const double *v) {
+  double m = 0.0;
+  for (int32_t i = 0; i < n; ++i)
+    if (fabs(v[i]) > m) m = fabs(v[i]);
+  return m;
+}
+
+int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg_fn fg, void *ctx,
+                     double *f_out, int32_t *iters_out, double *f_trace) {
+  if (n < 1 || !o || o->m < 1 || o->nonmonotone < 1 || o->max_ls < 1 || o->n_iter < 0) return -1;
+  const int32_t m = o->m, M = o->nonmonotone;
+  double *g = (double *)malloc(sizeof(double) * n), *d = (double *)malloc(sizeof(double) * n);
+  double *xn = (double *)malloc(sizeof(double) * n), *gn = (double *)malloc(sizeof(double) * n);
+  double *S = (double *)malloc(sizeof(double) * (size_t)m * n);
+  double *Y = (double *)malloc(sizeof(double) * (size_t)m * n);
+  double *fh = (double *)malloc(sizeof(double) * M);
+  double f;
+  fg(ctx, x, &f, g);
+  if (f_trace) f_trace[0] = f;
+  int32_t k = 0, nf = 1, it = 0, status = 1;
+  fh[0] = f;
+  for (it = 0; it < o->n_iter; ++it) {
+    double gmax = max_abs(n, g);
+    if (gmax <= o->gtol) { status = 0; break; }
+    /* search direction */
+    double gamma = o->step0 / gmax;
+    if (k > 0) {
+      const double *s = S + (size_t)(k - 1) * n, *y = Y + (size_t)(k - 1) * n;
+      gamma = dotn(n, s, y) / dotn(n, y, y);
+    }
+    oracle_lbfgs_direction(n, k, S, Y, g, gamma, d);
+    double gd = dotn(n, g, d);
+    if (!(gd < 0.0)) { /* not a descent direction: drop the history, scaled steepest descent */
+      k = 0;
+      gamma = o->step0 / gmax;
+      for (int32_t e = 0; e < n; ++e) d[e] = -gamma * g[e];
+      gd = dotn(n, g, d);
+    }
+    /* Armijo backtracking against the largest of the last M accepted values */
+    double fref = fh[0];
+    for (int32_t i = 1; i < (nf < M ? nf : M); ++i)
+      if (fh[i] > fref) fref = fh[i];
+    double alpha = 1.0, fnew = 0.0;
+    int32_t ok = 0;
+    for (int32_t ls = 0; ls < o->max_ls; ++ls) {
+      for (int32_t e = 0; e < n; ++e) xn[e] = x[e] + alpha * d[e];
+      fg(ctx, xn, &fnew, gn);
+      if (fnew <= fref + o->c1 * alpha * gd) { ok = 1; break; }
+      alpha *= o->shrink;
+    }
+    if (!ok) { status = 2; break; }
+    /* curvature pair s = xn - x, y = gn - g, kept only when s.y is clearly positive;
+     * with a full history the oldest pair makes room */
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int32_t e = 0; e < n; ++e) {
+      double se = xn[e] - x[e], ye = gn[e] - g[e];
+      sy += se * ye; ss += se * se; yy += ye * ye;
+    }
+    if (sy > 1e-8 * sqrt(ss * yy)) {
+      if (k == m) {
+        memmove(S, S + n, sizeof(double) * (size_t)(m - 1) * n);
+        memmove(Y, Y + n, sizeof(double) * (size_t)(m - 1) * n);
+        --k;
+      }
+      for (int32_t e = 0; e < n; ++e) {
+        S[(size_t)k * n + e] = xn[e] - x[e];
+        Y[(size_t)k * n + e] = gn[e] - g[e];
+      }
+      ++k;
+    }
+    memcpy(x, xn, sizeof(double) * n);
+    memcpy(g, gn, sizeof(double) * n);
+    f = fnew;
+    fh[nf % M] = f;
+    ++nf;
+    if (f_trace) f_trace[it + 1] = f;
+  }
+  if (f_out) *f_out = f;
+  if (iters_out) *iters_out = it;
+  free(g); free(d); free(xn); free(gn); free(S); free(Y); free(fh);
+  return status;
+}
+
+typedef struct {
+  const oracle_cfg *cfg;
+  const double *y;
+} protein_fg_ctx;
+
+static void protein_fg(void *ctx, const double *x, double *f, double *g) {
+  const protein_fg_ctx *p = (const protein_fg_ctx *)ctx;
+  oracle_grad(p->cfg, p->y, x, f, g);
+}
+
+int32_t oracle_lbfgs_protein(const oracle_cfg *cfg, const double *y, double *s,
+                             const oracle_lbfgs_opts *o, double *V_out, int32_t *iters_out,
+                             double *f_trace) {
+  if (!cfg || cfg->L < 2) return -1;
+  protein_fg_ctx p = {cfg, y};
+  int32_t st = oracle_lbfgs(2 * cfg->L, s, o, protein_fg, &p, V_out, iters_out, f_trace);
+  for (int32_t k = 0; k < 2 * cfg->L; ++k) s[k] = wrap_angle(s[k]);
+  return st;
+}

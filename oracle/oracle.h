@@ -86,6 +86,34 @@ double oracle_delta_e(const oracle_cfg *cfg, const double *y, const double *s, i
 /* Gradient of V with respect to s (analytic, by the rotation argument). */
 void oracle_grad(const oracle_cfg *cfg, const double *y, const double *s, double *V_out, double *g);
 
+/* L-BFGS with a (nonmonotone) Armijo backtracking line search.
+ *   n_iter       accepted iterations at most;  m  stored curvature pairs (>= 1);
+ *   nonmonotone  M >= 1: trial accepted iff f(x + a d) <= max(last M accepted f) + c1 a g.d;
+ *   max_ls       trials per line search (a = 1, shrink, shrink^2, ...);
+ *   gtol         stop when max|g| <= gtol;
+ *   step0        with no stored pair the direction is -(step0 / max|g|) g.
+ * A curvature pair (s, y) is stored iff s.y > 1e-8 |s| |y|; a direction with g.d >= 0
+ * drops the history.  Returns 0 (gtol reached), 1 (iteration limit), 2 (line search
+ * failed; x is the last accepted point) or -1 (invalid options). */
+typedef struct {
+  int32_t n_iter, m, nonmonotone, max_ls;
+  double c1, shrink, gtol, step0;
+} oracle_lbfgs_opts;
+
+typedef void (*oracle_fg_fn)(void *ctx, const double *x, double *f, double *g);
+
+/* d = -H g by the two-loop recursion over k pairs (oldest first) from H0 = gamma I. */
+void oracle_lbfgs_direction(int32_t n, int32_t k, const double *S, const double *Y,
+                            const double *g, double gamma, double *d);
+/* Minimise fg from x (in/out).  f_trace [n_iter + 1] or NULL receives f(x0) and the
+ * value after each accepted iteration. */
+int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg_fn fg, void *ctx,
+                     double *f_out, int32_t *iters_out, double *f_trace);
+/* Minimise V(s) of a protein; s is wrapped into (-pi, pi] on return. */
+int32_t oracle_lbfgs_protein(const oracle_cfg *cfg, const double *y, double *s,
+                             const oracle_lbfgs_opts *o, double *V_out, int32_t *iters_out,
+                             double *f_trace);
+
 /* Initialise chain state: v[2c] = v[2c+1] = V(s0_c), s_best = s. */
 void oracle_chain_init(const oracle_cfg *cfg, const double *y, int32_t n_chains,
                        const double *s, double *s_best, double *v);
