@@ -89,6 +89,83 @@ def gpu_leg(w, steps, warmup, G=0, W=0):
                 v=v, counters=cnt)
 
 
+def batch_leg(steps, warmup, n_proteins, tune_sweeps):
+    """Ragged batch (lengths uniform on [50, 600], 256 chains each): one cycle of all
+    proteins in batched launches against the same cycle as one plain launch per
+    protein.  Both sides start from the same state and follow the same trajectories
+    (bit for bit), so equal final energies are checked exactly."""
+    import torch
+    from paper_2211_03193_amd import amh
+
+    dev = torch.device("cuda:0")
+    ws = sy.batch_workloads(n=n_proteins)
+    cyc = ws[0].global_every
+    ys, vref = [], []
+    for w in ws:
+        s_ref = sy.reference_torsions(w.L, w.protein_seed)
+        atoms = amh.conformation(torch.from_numpy(s_ref[None]).to(dev))[0].cpu().numpy()
+        y = sy.distogram(sy.pair_distances(atoms[:, 3, :]), w.eps, w.noise_seed)
+        ys.append(torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(dev))
+    A = [amh.Context(amh.make_config(w), y) for w, y in zip(ws, ys)]
+    B = [amh.Context(amh.make_config(w), y) for w, y in zip(ws, ys)]
+    for w, y, a, b in zip(ws, ys, A, B):
+        s_ref = torch.from_numpy(sy.reference_torsions(w.L, w.protein_seed)[None]).to(dev)
+        v = a.energy(s_ref)[0].item()
+        vref.append(v)
+        a.set_target(1.05 * v)
+        b.set_target(1.05 * v)
+    batch = amh.Batch(A)
+    plan, trial_ms = batch.tune(tune_sweeps)
+    for b in B:                      # the tuning sweeps, as plain launches
+        b.sweep(6 * tune_sweeps)
+    for _ in range(warmup):
+        batch.sweep(cyc)
+        for b in B:
+            b.sweep(cyc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.sweep(cyc)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for b in B:
+            b.sweep(cyc)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = True
+    best_a, best_b = [], []
+    for a, b in zip(A, B):
+        sa, sb = a.get_state(), b.get_state()
+        same &= all(torch.equal(sa[k], sb[k]) for k in ("s", "s_best", "v", "counters"))
+        best_a.append(sa["v"][:, 1].min().item())
+        best_b.append(sb["v"][:, 1].min().item())
+    info = batch.info()
+    batch.close()
+    props = sum(w.n_chains * 2 * w.L for w in ws) * cyc * steps
+    pairs = sum(w.n_chains * sum(pair_evals_per_cycle(w.L, w.window_d, cyc)) for w in ws) * steps
+    for c in A + B:
+        c.close()
+    return {
+        "metric": "proposals/s", "value": props / t_batch, "unit": "proposals/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": t_batch * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch-{len(ws)}proteins-L50-600-256chains",
+                   "lengths": [w.L for w in ws], "chains_per_protein": ws[0].n_chains,
+                   "window_d": ws[0].window_d, "global_every": cyc, "sweeps_per_step": cyc,
+                   "tune_sweeps_per_plan": tune_sweeps, "plan": plan, "plan_trial_ms": trial_ms,
+                   "launches_per_step": info["launches"], "workgroups": info["workgroups"]},
+        "pair_evals_per_s": pairs / t_batch,
+        "plain_launches": {"value": props / t_plain, "unit": "proposals/s",
+                           "ms_per_step": t_plain * 1e3 / steps},
+        "speedup_vs_plain": t_plain / t_batch,
+        "same_trajectories_as_plain": bool(same),
+        "best_energy_equal": best_a == best_b,
+    }
+
+
 def cpu_leg(w, cores, sweeps):
     import oracle
     s_ref = sy.reference_torsions(w.L, w.protein_seed)
@@ -117,6 +194,11 @@ def main():
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=80)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
+    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+                    help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
+                         "of lengths 50-600, 256 chains each, batched vs plain launches")
+    ap.add_argument("--proteins", type=int, default=64, help="proteins in the batch workload")
+    ap.add_argument("--tune-sweeps", type=int, default=10, help="sweeps per autotuner trial")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -135,6 +217,11 @@ def main():
               "GPUs with no per-step communication, see the design notes.", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.workload == "batch":
+        out = batch_leg(args.steps, args.warmup, args.proteins, args.tune_sweeps)
+        if rank == 0:
+            print(json.dumps(out), flush=True)
+        return
     w = sy.CFG2
     cyc = w.global_every
     if (args.warmup + args.steps) * cyc > w.total_sweeps:

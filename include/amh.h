@@ -136,12 +136,146 @@ amh_status amh_poll(amh_ctx* ctx);
 amh_status amh_info(amh_ctx* ctx, int32_t* chains_per_group, int32_t* waves_per_group,
                     int32_t* lds_bytes, int64_t* t);
 
-/* Gradient dV/ds of B conformations (the adjoint of G and the spline energy). */
+/* Energy and gradient dV/ds of B conformations, in float64 (the distogram energy
+ * of Sec. 2.3 through the geometry G(s) of Sec. 2.1; the paper minimises the same
+ * energy with L-BFGS, Sec. 3).  Turning torsion k moves the residues from its pivot
+ * on rigidly about the bond axis, so dV/ds_k = u_k . sum_{j >= p} (x_j - a_k) x F_j
+ * with F_j = dV/dx_j (C-beta forces); dV/ds is zero for phi_0 and psi_{L-1}.
+ *   s_dev      [B][2L] torsions, or NULL for the context's current chains (B must
+ *              equal n_chains);
+ *   V_out_dev  [B] or NULL;  g_out_dev [B][2L] or NULL (not both NULL).
+ * Non-finite energies raise AMH_E_NUMERIC at the next amh_poll. */
 amh_status amh_grad(amh_ctx* ctx, const double* s_dev, int32_t B, double* V_out_dev,
                     double* g_out_dev);
 
-/* Serving: admit a folding job into a running server (continuous batching). */
+/* Options of amh_minimize (all validated on the host; AMH_E_INVAL otherwise). */
+typedef struct {
+  int32_t n_iter;       /* accepted iterations at most, >= 0 */
+  int32_t m;            /* curvature pairs kept, 1 .. 64 */
+  int32_t nonmonotone;  /* M, 1 .. 64: a trial step is accepted iff
+                           V(s + a d) <= max(last M accepted V) + c1 a g.d (M = 1: monotone) */
+  int32_t max_ls;       /* trial steps a = 1, shrink, shrink^2, ... per iteration, >= 1 */
+  double c1;            /* Armijo constant in (0, 1) */
+  double shrink;        /* backtracking factor in (0, 1) */
+  double gtol;          /* stop once max |dV/ds| <= gtol (>= 0) */
+  double step0;         /* with no curvature pair the direction is -(step0 / max|g|) g (> 0, rad) */
+} amh_lbfgs_opts;
+
+/* L-BFGS minimisation of V(s) (Liu and Nocedal 1989, two-loop recursion) with a
+ * nonmonotone Armijo backtracking line search (Grippo, Lampariello and Lucidi 1986),
+ * the minimiser the paper pairs with its sampler (Sec. 3, Fig. 3).  A curvature pair
+ * (s, y) is kept iff s.y > 1e-8 |s| |y|; a direction with g.d >= 0 drops the history.
+ * One workgroup per conformation; a float64 workspace of B (5 + 2m) 2L doubles is
+ * allocated by the context on first use (and grown, after a stream synchronisation).
+ *   s_dev          [B][2L] in/out, or NULL for the context's current chains (B must
+ *                  equal n_chains): then the chains' current V, best V / best state and
+ *                  coordinates are updated, so sampling can continue from the minimum;
+ *   V_out_dev      [B] final V or NULL;  iters_out_dev [B] accepted iterations or NULL;
+ *   status_out_dev [B] or NULL: 0 gradient below gtol, 1 iteration limit, 2 line
+ *                  search failed (the last accepted point is returned);
+ *   f_trace_dev    [B][n_iter + 1] or NULL: V at the start and after each accepted
+ *                  iteration (entries past the last iteration are left untouched);
+ *   x_trace_dev    [B][n_iter + 1][2L] or NULL: the iterates themselves (not wrapped),
+ *                  likewise; for step-by-step checks.
+ * Torsions are returned wrapped into (-pi, pi]. */
+amh_status amh_minimize(amh_ctx* ctx, double* s_dev, int32_t B, const amh_lbfgs_opts* opts,
+                        double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
+                        double* f_trace_dev, double* x_trace_dev);
+
+/* ---- Serving: a continuous-batching request loop --------------------------------
+ * Folding jobs (one protein each) are queued by amh_submit and admitted in arrival
+ * order while a slot is free and the device memory they need fits the budget.
+ * Each amh_server_step advances every admitted job by sweeps_per_round sweeps in
+ * shared batched launches (jobs of different lengths side by side), reads back each
+ * job's counters, retires jobs that reached their target energy or their last sweep
+ * (keeping a host copy of the best state) and admits waiting jobs into the freed
+ * memory.  Chain state stays on the device between steps.  A job's sweeps do not
+ * depend on the other jobs in its launches: its result is the same alone and in the
+ * mix.  One host thread drives a server. */
+typedef struct amh_server amh_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* device bytes admitted jobs may hold (tables + chain state) */
+  int32_t max_active;       /* admitted jobs at most (1 = one job at a time, in order) */
+  int32_t sweeps_per_round; /* sweeps per job per amh_server_step, >= 1 */
+  int32_t plan;             /* launch plan of the shared launches, 0..5 (see amh_batch_tune) */
+  int32_t reserved;
+} amh_server_opts;
+
+typedef struct {
+  amh_config cfg;        /* the job's run, with its own seed (Philox key) */
+  const float* y_host;   /* [L(L-1)/2][n_bins] -ln p in host memory, copied by amh_submit */
+  double target;         /* the job ends at the first anchor where a chain has V <= target */
+} amh_job;
+
+typedef struct {
+  int32_t state;            /* 0 waiting, 1 admitted, 2 done, 3 failed */
+  int32_t reached;          /* 1 once a chain reached the target */
+  int64_t sweeps;           /* sweeps run so far */
+  int64_t sweeps_to_target; /* smallest sweep count at which a chain reached it, or -1 */
+  double best_V;            /* lowest anchored energy over the chains (after a step) */
+  double t_submit, t_admit, t_target, t_done; /* seconds, steady clock; -1 until they happen */
+  int64_t bytes;            /* device bytes the job holds while admitted (budget accounting) */
+} amh_job_status;
+
+/* Create a server whose work is ordered on `stream` (a hipStream_t, NULL = default). */
+amh_status amh_server_create(const amh_server_opts* opts, void* stream, amh_server** out);
+
+/* Queue a job (job points to an amh_job); *job_id receives its handle.  The table is
+ * copied: the caller may free y_host on return.  AMH_E_BUSY if the job alone needs
+ * more than the whole budget; AMH_E_INVAL for an invalid job. */
 amh_status amh_submit(void* server, const void* job, uint64_t* job_id);
+
+/* One round: admit, advance every admitted job, retire finished ones.  Synchronises
+ * the stream once per round (to read the jobs' counters back). */
+amh_status amh_server_step(amh_server* server, int32_t* n_active, int32_t* n_pending);
+
+/* Status of a job; s_best_host [C][2L] (done jobs only) and v_host [C][2] = (V at the
+ * last anchor, best V) per chain may be NULL. */
+amh_status amh_server_job(amh_server* server, uint64_t job_id, amh_job_status* out,
+                          double* s_best_host, double* v_host);
+
+/* Synchronise and free the server and every job it holds. */
+amh_status amh_server_destroy(amh_server* server);
+
+/* ---- Batches: many proteins (contexts of different L) in one launch ----------
+ * The chains of every member context are independent (Sec. 2.4, inter-block
+ * parallelism), so one launch can advance the chains of several proteins: each
+ * workgroup runs one chain group of one member, with the LDS of the launch sized
+ * for its longest member and the grid ordered by decreasing work per workgroup.
+ * Members with different launch shapes (chains per workgroup, wavefronts) are
+ * advanced by one launch per shape.  Trajectories do not depend on the launch
+ * shape or on the batch: a member advanced in a batch follows exactly the sweeps
+ * it would follow alone (same Philox counters, same arithmetic). */
+typedef struct amh_batch amh_batch;
+
+/* Group n >= 1 distinct contexts created on one stream.  The batch borrows them:
+ * they stay owned by the caller, must outlive the batch, and remain usable alone
+ * (amh_energy, amh_get_state, ...). */
+amh_status amh_batch_create(amh_ctx* const* ctxs, int32_t n, amh_batch** out);
+
+/* Advance every member by n_sweeps >= 0 sweeps (each member's own schedule from its
+ * own sweep counter); AMH_E_INVAL if any member would pass its total_sweeps. */
+amh_status amh_batch_sweep(amh_batch* batch, int64_t n_sweeps);
+
+/* Autotuner: time each launch plan on sweeps_per_trial real sweeps of every member
+ * (they count as part of the run: 6 * sweeps_per_trial sweeps in all), keep the
+ * fastest.  Plans: 0 = each context's own shape; 1..5 = (chains per workgroup,
+ * wavefronts) of (1,4), (2,4), (2,8), (4,4), (4,8), with fewer chains per workgroup
+ * for members whose length does not fit the LDS.  ms_out [6] (or NULL) receives the
+ * time of each trial, *plan_out (or NULL) the plan kept. */
+amh_status amh_batch_tune(amh_batch* batch, int64_t sweeps_per_trial, float* ms_out,
+                          int32_t* plan_out);
+
+/* Select a launch plan (0..5, as above) without timing. */
+amh_status amh_batch_set_plan(amh_batch* batch, int32_t plan);
+
+/* Current plan, number of launches per sweep call and total workgroups. */
+amh_status amh_batch_info(const amh_batch* batch, int32_t* plan, int32_t* n_launches,
+                          int32_t* workgroups);
+
+/* Synchronise the stream and free the batch (not its members). */
+amh_status amh_batch_destroy(amh_batch* batch);
 
 amh_status amh_destroy(amh_ctx* ctx);
 const char* amh_last_error(void);

@@ -38,6 +38,14 @@ def lbfgs_opts(n_iter=200, m=8, nonmonotone=5, max_ls=30, c1=1e-4, shrink=0.5, g
                      shrink=shrink, gtol=gtol, step0=step0)
 
 
+class LbfgsReplayReport(C.Structure):
+    _fields_ = [("n_steps", C.c_int64), ("n_forks", C.c_int64), ("n_fail", C.c_int64),
+                ("first_fail", C.c_int64), ("max_step_err", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 FG_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                     C.POINTER(C.c_double))
 
@@ -108,11 +116,14 @@ def lib():
     L.oracle_grad.argtypes = [P(Cfg), _D, _D, P(C.c_double), _D]
     L.oracle_lbfgs_direction.argtypes = [C.c_int32, C.c_int32, _D, _D, _D, C.c_double, _D]
     L.oracle_lbfgs.argtypes = [C.c_int32, _D, P(LbfgsOpts), FG_FN, C.c_void_p, P(C.c_double),
-                               P(C.c_int32), _opt(_D)]
+                               P(C.c_int32), _opt(_D), _opt(_D)]
     L.oracle_lbfgs.restype = C.c_int32
     L.oracle_lbfgs_protein.argtypes = [P(Cfg), _D, _D, P(LbfgsOpts), P(C.c_double), P(C.c_int32),
-                                       _opt(_D)]
+                                       _opt(_D), _opt(_D)]
     L.oracle_lbfgs_protein.restype = C.c_int32
+    L.oracle_lbfgs_replay.argtypes = [P(Cfg), _D, C.c_int32, _D, P(LbfgsOpts), C.c_double,
+                                      C.c_double, P(LbfgsReplayReport)]
+    L.oracle_lbfgs_replay.restype = C.c_int32
     L.oracle_chain_init.argtypes = [P(Cfg), _D, C.c_int32, _D, _D, _D]
     L.oracle_run.argtypes = [P(Cfg), _D, C.c_int32, _opt(_U32), C.c_int64, C.c_int64, C.c_int32,
                              C.c_int32, _D, _D, _D, _I64, C.c_double, _opt(_D), _opt(_U8),
@@ -247,19 +258,32 @@ def lbfgs(fg, x0, opts: LbfgsOpts | None = None):
     cb = FG_FN(_cb)
     f, it = C.c_double(), C.c_int32()
     tr = np.full(opts.n_iter + 1, np.nan)
-    st = lib().oracle_lbfgs(n, x, C.byref(opts), cb, None, C.byref(f), C.byref(it), tr)
+    st = lib().oracle_lbfgs(n, x, C.byref(opts), cb, None, C.byref(f), C.byref(it), tr, None)
     return x, f.value, it.value, st, tr[: it.value + 1]
 
 
-def lbfgs_protein(cfg: Cfg, y, s0, opts: LbfgsOpts | None = None):
-    """L-BFGS on V(s); returns (s wrapped, V, iters, status, f_trace)."""
+def lbfgs_protein(cfg: Cfg, y, s0, opts: LbfgsOpts | None = None, iterates: bool = False):
+    """L-BFGS on V(s); returns (s wrapped, V, iters, status, f_trace[, x_trace])."""
     opts = opts or lbfgs_opts()
     s = _f64(s0).copy()
     V, it = C.c_double(), C.c_int32()
     tr = np.full(opts.n_iter + 1, np.nan)
+    xt = np.full((opts.n_iter + 1, s.size), np.nan) if iterates else None
     st = lib().oracle_lbfgs_protein(C.byref(cfg), _f64(y), s, C.byref(opts), C.byref(V),
-                                    C.byref(it), tr)
-    return s, V.value, it.value, st, tr[: it.value + 1]
+                                    C.byref(it), tr, xt)
+    out = (s, V.value, it.value, st, tr[: it.value + 1])
+    return out + (xt[: it.value + 1],) if iterates else out
+
+
+def lbfgs_replay(cfg: Cfg, y, X, opts: LbfgsOpts | None = None, step_tol: float = 1e-6,
+                 tie_tol: float = 1e-9) -> tuple[int, dict]:
+    """Check device L-BFGS iterates X [n_it + 1][2L] step by step (see oracle.c)."""
+    opts = opts or lbfgs_opts()
+    X = _f64(X)
+    rep = LbfgsReplayReport()
+    rc = lib().oracle_lbfgs_replay(C.byref(cfg), _f64(y), X.shape[0] - 1, X.ravel(), C.byref(opts),
+                                   step_tol, tie_tol, C.byref(rep))
+    return rc, rep.as_dict()
 
 
 class Chains:

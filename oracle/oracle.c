@@ -624,7 +624,7 @@ static double max_abs(int32_t n, const double *v) {
 }
 
 int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg_fn fg, void *ctx,
-                     double *f_out, int32_t *iters_out, double *f_trace) {
+                     double *f_out, int32_t *iters_out, double *f_trace, double *x_trace) {
   if (n < 1 || !o || o->m < 1 || o->nonmonotone < 1 || o->max_ls < 1 || o->n_iter < 0) return -1;
   const int32_t m = o->m, M = o->nonmonotone;
   double *g = (double *)malloc(sizeof(double) * n), *d = (double *)malloc(sizeof(double) * n);
@@ -635,6 +635,7 @@ int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg
   double f;
   fg(ctx, x, &f, g);
   if (f_trace) f_trace[0] = f;
+  if (x_trace) memcpy(x_trace, x, sizeof(double) * n);
   int32_t k = 0, nf = 1, it = 0, status = 1;
   fh[0] = f;
   for (it = 0; it < o->n_iter; ++it) {
@@ -692,6 +693,7 @@ int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg
     fh[nf % M] = f;
     ++nf;
     if (f_trace) f_trace[it + 1] = f;
+    if (x_trace) memcpy(x_trace + (size_t)(it + 1) * n, x, sizeof(double) * n);
   }
   if (f_out) *f_out = f;
   if (iters_out) *iters_out = it;
@@ -711,10 +713,122 @@ static void protein_fg(void *ctx, const double *x, double *f, double *g) {
 
 int32_t oracle_lbfgs_protein(const oracle_cfg *cfg, const double *y, double *s,
                              const oracle_lbfgs_opts *o, double *V_out, int32_t *iters_out,
-                             double *f_trace) {
+                             double *f_trace, double *x_trace) {
   if (!cfg || cfg->L < 2) return -1;
   protein_fg_ctx p = {cfg, y};
-  int32_t st = oracle_lbfgs(2 * cfg->L, s, o, protein_fg, &p, V_out, iters_out, f_trace);
+  int32_t st = oracle_lbfgs(2 * cfg->L, s, o, protein_fg, &p, V_out, iters_out, f_trace, x_trace);
   for (int32_t k = 0; k < 2 * cfg->L; ++k) s[k] = wrap_angle(s[k]);
   return st;
+}
+
+/* Step-by-step check of a device L-BFGS run: X [n_it + 1][n] are the device's
+ * iterates.  For each k the oracle rebuilds its own state at X[k] (values and
+ * gradients at the device's iterates, curvature pairs from consecutive iterates,
+ * the same storage and reset rules), takes one iteration (direction and line
+ * search) and compares its step with X[k+1] - X[k]:
+ *   |dx_dev - dx_or|_inf <= step_tol |dx_or|_inf,
+ * or, if the device stopped its line search at another trial, the Armijo test
+ * that separates the two trials must be a near-tie (|f - threshold| <= tie_tol
+ * (|f_ref| + 1)), counted as a fork.  The replay always continues from X[k+1]. */
+int32_t oracle_lbfgs_replay(const oracle_cfg *cfg, const double *y, int32_t n_it, const double *X,
+                            const oracle_lbfgs_opts *o, double step_tol, double tie_tol,
+                            oracle_lbfgs_replay_report *rep) {
+  if (!cfg || !o || !X || !rep || n_it < 0 || o->m < 1 || o->nonmonotone < 1 || o->max_ls < 1) return -1;
+  const int32_t n = 2 * cfg->L, m = o->m, M = o->nonmonotone;
+  memset(rep, 0, sizeof(*rep));
+  rep->first_fail = -1;
+  double *g = (double *)malloc(sizeof(double) * n), *gn = (double *)malloc(sizeof(double) * n);
+  double *d = (double *)malloc(sizeof(double) * n), *xt = (double *)malloc(sizeof(double) * n);
+  double *gt = (double *)malloc(sizeof(double) * n);
+  double *S = (double *)malloc(sizeof(double) * (size_t)m * n);
+  double *Y = (double *)malloc(sizeof(double) * (size_t)m * n);
+  double *fh = (double *)malloc(sizeof(double) * M);
+  double *fl = (double *)malloc(sizeof(double) * o->max_ls);
+  double f, fn;
+  oracle_grad(cfg, y, X, &f, g);
+  fh[0] = f;
+  int32_t k = 0, nf = 1;
+  for (int32_t it = 0; it < n_it; ++it) {
+    const double *x = X + (size_t)it * n, *xn = X + (size_t)(it + 1) * n;
+    double gmax = max_abs(n, g);
+    double gamma = o->step0 / gmax;
+    if (k > 0) gamma = dotn(n, S + (size_t)(k - 1) * n, Y + (size_t)(k - 1) * n) /
+                       dotn(n, Y + (size_t)(k - 1) * n, Y + (size_t)(k - 1) * n);
+    oracle_lbfgs_direction(n, k, S, Y, g, gamma, d);
+    double gd = dotn(n, g, d);
+    if (!(gd < 0.0)) {
+      k = 0;
+      gamma = o->step0 / gmax;
+      for (int32_t e = 0; e < n; ++e) d[e] = -gamma * g[e];
+      gd = dotn(n, g, d);
+    }
+    double fref = fh[0];
+    for (int32_t i = 1; i < (nf < M ? nf : M); ++i)
+      if (fh[i] > fref) fref = fh[i];
+    /* the oracle's line search, keeping every trial's Armijo margin */
+    int32_t j_or = -1;
+    double alpha = 1.0;
+    for (int32_t j = 0; j < o->max_ls; ++j) {
+      for (int32_t e = 0; e < n; ++e) xt[e] = x[e] + alpha * d[e];
+      oracle_grad(cfg, y, xt, &fl[j], gt);
+      fl[j] -= fref + o->c1 * alpha * gd;   /* margin: accepted iff <= 0 */
+      if (fl[j] <= 0.0) { j_or = j; break; }
+      alpha *= o->shrink;
+    }
+    /* which trial did the device take? */
+    double dnorm = max_abs(n, d), best = INFINITY;
+    int32_t j_dev = -1;
+    double a = 1.0;
+    for (int32_t j = 0; j < o->max_ls; ++j, a *= o->shrink) {
+      double e_max = 0.0;
+      for (int32_t e = 0; e < n; ++e) {
+        double q = fabs((xn[e] - x[e]) - a * d[e]);
+        if (q > e_max) e_max = q;
+      }
+      double rel = e_max / (a * dnorm > 0.0 ? a * dnorm : 1.0);
+      if (rel < best) { best = rel; j_dev = j; }
+    }
+    int32_t bad = 0;
+    if (j_dev == j_or) {
+      if (best > rep->max_step_err) rep->max_step_err = best;
+      if (!(best <= step_tol)) bad = 1;
+    } else if (j_or < 0 || j_dev < 0 || best > step_tol) {
+      bad = 1;
+    } else {
+      /* the first trial where the two searches disagree must be a near-tie */
+      int32_t jm = j_dev < j_or ? j_dev : j_or;
+      if (fabs(fl[jm]) <= tie_tol * (fabs(fref) + 1.0)) rep->n_forks++;
+      else bad = 1;
+    }
+    if (bad) {
+      rep->n_fail++;
+      if (rep->first_fail < 0) rep->first_fail = it;
+    }
+    /* continue from the device's iterate */
+    oracle_grad(cfg, y, xn, &fn, gn);
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int32_t e = 0; e < n; ++e) {
+      double se = xn[e] - x[e], ye = gn[e] - g[e];
+      sy += se * ye; ss += se * se; yy += ye * ye;
+    }
+    if (sy > 1e-8 * sqrt(ss * yy)) {
+      if (k == m) {
+        memmove(S, S + n, sizeof(double) * (size_t)(m - 1) * n);
+        memmove(Y, Y + n, sizeof(double) * (size_t)(m - 1) * n);
+        --k;
+      }
+      for (int32_t e = 0; e < n; ++e) {
+        S[(size_t)k * n + e] = xn[e] - x[e];
+        Y[(size_t)k * n + e] = gn[e] - g[e];
+      }
+      ++k;
+    }
+    memcpy(g, gn, sizeof(double) * n);
+    f = fn;
+    fh[nf % M] = f;
+    ++nf;
+    rep->n_steps++;
+  }
+  free(g); free(gn); free(d); free(xt); free(gt); free(S); free(Y); free(fh); free(fl);
+  return rep->n_fail ? 1 : 0;
 }

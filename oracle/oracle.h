@@ -105,14 +105,27 @@ typedef void (*oracle_fg_fn)(void *ctx, const double *x, double *f, double *g);
 /* d = -H g by the two-loop recursion over k pairs (oldest first) from H0 = gamma I. */
 void oracle_lbfgs_direction(int32_t n, int32_t k, const double *S, const double *Y,
                             const double *g, double gamma, double *d);
-/* Minimise fg from x (in/out).  f_trace [n_iter + 1] or NULL receives f(x0) and the
- * value after each accepted iteration. */
+/* Minimise fg from x (in/out).  f_trace [n_iter + 1] and x_trace [n_iter + 1][n] (or
+ * NULL) receive f and x at the start and after each accepted iteration. */
 int32_t oracle_lbfgs(int32_t n, double *x, const oracle_lbfgs_opts *o, oracle_fg_fn fg, void *ctx,
-                     double *f_out, int32_t *iters_out, double *f_trace);
-/* Minimise V(s) of a protein; s is wrapped into (-pi, pi] on return. */
+                     double *f_out, int32_t *iters_out, double *f_trace, double *x_trace);
+/* Minimise V(s) of a protein; s is wrapped into (-pi, pi] on return (x_trace is not). */
 int32_t oracle_lbfgs_protein(const oracle_cfg *cfg, const double *y, double *s,
                              const oracle_lbfgs_opts *o, double *V_out, int32_t *iters_out,
-                             double *f_trace);
+                             double *f_trace, double *x_trace);
+
+/* Step-by-step check of a device L-BFGS run from its iterates X [n_it + 1][2L]
+ * (see oracle.c): returns 0 if every step matches, 1 otherwise, -1 on bad input. */
+typedef struct {
+  int64_t n_steps;     /* iterations checked */
+  int64_t n_forks;     /* line searches that stopped at another trial at a near-tie */
+  int64_t n_fail;      /* steps that differ beyond step_tol and are not forks */
+  int64_t first_fail;  /* -1 if none */
+  double max_step_err; /* max |dx_dev - dx_or|_inf / |dx_or|_inf over matched steps */
+} oracle_lbfgs_replay_report;
+int32_t oracle_lbfgs_replay(const oracle_cfg *cfg, const double *y, int32_t n_it, const double *X,
+                            const oracle_lbfgs_opts *o, double step_tol, double tie_tol,
+                            oracle_lbfgs_replay_report *rep);
 
 /* Initialise chain state: v[2c] = v[2c+1] = V(s0_c), s_best = s. */
 void oracle_chain_init(const oracle_cfg *cfg, const double *y, int32_t n_chains,

@@ -37,6 +37,39 @@ class AmhConfig(C.Structure):
     ]
 
 
+class LbfgsOpts(C.Structure):
+    _fields_ = [
+        ("n_iter", C.c_int32), ("m", C.c_int32), ("nonmonotone", C.c_int32), ("max_ls", C.c_int32),
+        ("c1", C.c_double), ("shrink", C.c_double), ("gtol", C.c_double), ("step0", C.c_double),
+    ]
+
+
+def lbfgs_opts(n_iter=200, m=8, nonmonotone=5, max_ls=30, c1=1e-4, shrink=0.5, gtol=1e-6,
+               step0=0.1) -> LbfgsOpts:
+    """amh_lbfgs_opts with the defaults used throughout (see include/amh.h)."""
+    return LbfgsOpts(n_iter=n_iter, m=m, nonmonotone=nonmonotone, max_ls=max_ls, c1=c1,
+                     shrink=shrink, gtol=gtol, step0=step0)
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_active", C.c_int32),
+                ("sweeps_per_round", C.c_int32), ("plan", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("cfg", AmhConfig), ("y_host", C.c_void_p), ("target", C.c_double)]
+
+
+class JobStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("reached", C.c_int32), ("sweeps", C.c_int64),
+                ("sweeps_to_target", C.c_int64), ("best_V", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_target", C.c_double), ("t_done", C.c_double),
+                ("bytes", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -64,6 +97,17 @@ def lib():
         "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
         "amh_grad": [_P, _P, C.c_int32, _P, _P],
+        "amh_minimize": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
+        "amh_batch_create": [C.POINTER(_P), C.c_int32, C.POINTER(_P)],
+        "amh_batch_sweep": [_P, C.c_int64],
+        "amh_batch_tune": [_P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int32)],
+        "amh_batch_set_plan": [_P, C.c_int32],
+        "amh_batch_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "amh_batch_destroy": [_P],
+        "amh_server_create": [C.POINTER(ServerOpts), _P, C.POINTER(_P)],
+        "amh_server_step": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "amh_server_job": [_P, C.c_uint64, C.POINTER(JobStatus), _P, _P],
+        "amh_server_destroy": [_P],
         "amh_submit": [_P, _P, C.POINTER(C.c_uint64)],
         "amh_destroy": [_P],
         "amh_philox": [_P, C.c_int64, C.c_uint64, _P, _P],
@@ -150,6 +194,46 @@ class Context:
         check(lib().amh_energy(self._h, _ptr(s), B, which, _ptr(V), _ptr(so), _ptr(cb)))
         return V, so, cb
 
+    def _check_s(self, s):
+        if s is not None and (s.dtype != torch.float64 or not s.is_contiguous() or s.dim() != 2
+                              or s.shape[1] != 2 * self.L or not s.is_cuda):
+            raise ValueError("s must be a contiguous float64 CUDA tensor [B][2L]")
+
+    def grad(self, s: torch.Tensor | None = None):
+        """(V [B], dV/ds [B][2L]) in float64 of s [B][2L], or of the current chains."""
+        self._check_s(s)
+        B = self.C if s is None else s.shape[0]
+        V = torch.empty(B, dtype=torch.float64, device=self.device)
+        g = torch.empty(B, 2 * self.L, dtype=torch.float64, device=self.device)
+        if B > 0:   # an empty tensor has no address; NULL would mean the context's chains
+            check(lib().amh_grad(self._h, _ptr(s), B, _ptr(V), _ptr(g)))
+        return V, g
+
+    def minimize(self, s: torch.Tensor | None = None, opts: LbfgsOpts | None = None,
+                 trace: bool = False, iterates: bool = False) -> dict:
+        """L-BFGS on V (amh_minimize).  s [B][2L] is minimised in place; with s None the
+        context's current chains are (and their V, best state and coordinates follow)."""
+        self._check_s(s)
+        opts = opts or lbfgs_opts()
+        B = self.C if s is None else s.shape[0]
+        d = self.device
+        out = {"V": torch.empty(B, dtype=torch.float64, device=d),
+               "iters": torch.empty(B, dtype=torch.int32, device=d),
+               "status": torch.empty(B, dtype=torch.int32, device=d),
+               "trace": torch.full((B, opts.n_iter + 1), float("nan"), dtype=torch.float64, device=d)
+               if trace else None,
+               "x": torch.full((B, opts.n_iter + 1, 2 * self.L), float("nan"), dtype=torch.float64,
+                               device=d) if iterates else None}
+        if B > 0:   # an empty tensor has no address; NULL would mean the context's chains
+            check(lib().amh_minimize(self._h, _ptr(s), B, C.byref(opts), _ptr(out["V"]),
+                                     _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["trace"]),
+                                     _ptr(out["x"])))
+        return out
+
+    def energy_fn(self):
+        """V(s) as a differentiable function of s [B][2L] (torch.autograd)."""
+        return lambda s: _Energy.apply(s, self)
+
     def get_state(self) -> dict:
         n, Cc, L = 2 * self.L, self.C, self.L
         d = self.device
@@ -217,6 +301,119 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Several contexts (proteins of any lengths) advanced together (amh_batch_*)."""
+
+    N_PLANS = 6
+
+    def __init__(self, contexts):
+        self.members = list(contexts)
+        arr = (_P * len(self.members))(*[c._h for c in self.members])
+        self._h = C.c_void_p()
+        check(lib().amh_batch_create(arr, len(self.members), C.byref(self._h)))
+
+    def sweep(self, n: int) -> None:
+        check(lib().amh_batch_sweep(self._h, n))
+
+    def tune(self, sweeps_per_trial: int) -> tuple[int, list[float]]:
+        ms = (C.c_float * self.N_PLANS)()
+        plan = C.c_int32()
+        check(lib().amh_batch_tune(self._h, sweeps_per_trial, ms, C.byref(plan)))
+        return plan.value, list(ms)
+
+    def set_plan(self, plan: int) -> None:
+        check(lib().amh_batch_set_plan(self._h, plan))
+
+    def info(self) -> dict:
+        p, nl, wg = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().amh_batch_info(self._h, C.byref(p), C.byref(nl), C.byref(wg)))
+        return {"plan": p.value, "launches": nl.value, "workgroups": wg.value}
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().amh_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (amh_server_* and amh_submit)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 1 << 30, sweeps_per_round: int = 10,
+                 plan: int = 0, stream=None):
+        self.opts = ServerOpts(hbm_budget_bytes=int(hbm_budget_bytes), max_active=int(max_active),
+                               sweeps_per_round=int(sweeps_per_round), plan=int(plan), reserved=0)
+        self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
+        self._h = C.c_void_p()
+        self._cfg = {}
+        check(lib().amh_server_create(C.byref(self.opts), _stream(self._stream_obj), C.byref(self._h)))
+
+    def submit(self, cfg: AmhConfig, y, target: float) -> int:
+        """Queue a job: cfg (amh_config), y [L(L-1)/2][n_bins] float32 host array, target V."""
+        import numpy as np
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        if y.shape != (cfg.L * (cfg.L - 1) // 2, cfg.n_bins):
+            raise ValueError(f"y has shape {y.shape}")
+        job = Job(cfg=cfg, y_host=y.ctypes.data, target=float(target))
+        jid = C.c_uint64()
+        check(lib().amh_submit(self._h, C.byref(job), C.byref(jid)))
+        self._cfg[jid.value] = (cfg.n_chains, cfg.L)
+        return jid.value
+
+    def step(self) -> tuple[int, int]:
+        a, p = C.c_int32(), C.c_int32()
+        check(lib().amh_server_step(self._h, C.byref(a), C.byref(p)))
+        return a.value, p.value
+
+    def job(self, jid: int, want_state: bool = False) -> dict:
+        import numpy as np
+        st = JobStatus()
+        out = None
+        if want_state:
+            Cn, L = self._cfg[jid]
+            sb = np.empty((Cn, 2 * L))
+            v = np.empty((Cn, 2))
+            check(lib().amh_server_job(self._h, jid, C.byref(st), sb.ctypes.data, v.ctypes.data))
+            out = {"s_best": sb, "v": v}
+        else:
+            check(lib().amh_server_job(self._h, jid, C.byref(st), None, None))
+        d = st.as_dict()
+        if out:
+            d.update(out)
+        return d
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().amh_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Energy(torch.autograd.Function):
+    """V(s) with the hand-written adjoint of amh_grad as its backward."""
+
+    @staticmethod
+    def forward(ctx, s, sampler):
+        V, g = sampler.grad(s.detach().contiguous())
+        ctx.save_for_backward(g)
+        return V
+
+    @staticmethod
+    def backward(ctx, gV):
+        (g,) = ctx.saved_tensors
+        return gV[:, None] * g, None
 
 
 def conformation(s: torch.Tensor, stream=None) -> torch.Tensor:

@@ -6,17 +6,24 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "amh.h"
+#include "amh_error.h"
+#include "amh_grad.h"
 #include "amh_kernels.h"
 
+static_assert(sizeof(amh_config) == 96, "amh_config layout");
+static_assert(sizeof(amh_lbfgs_opts) == 48, "amh_lbfgs_opts layout");
+
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-amh_status fail(amh_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-amh_status fail(amh_status st, const char* fmt, ...) {
+namespace amh {
+amh_status sfail(amh_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -25,12 +32,17 @@ amh_status fail(amh_status st, const char* fmt, ...) {
   g_last_error = buf;
   return st;
 }
+}  // namespace amh
+
+namespace {
+
+using amh::sfail;
 
 #define HIP_OK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess)                                                              \
-      return fail(AMH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+      return sfail(AMH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
 
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
@@ -65,32 +77,35 @@ struct amh_ctx {
   int64_t trace_cap = 0, trace_t0 = 0;
   double* tr_anchor = nullptr;
   int64_t trace_anchor_cap = 0, trace_anchor0 = 0;
+  // L-BFGS workspace, grown on demand
+  double* work = nullptr;
+  size_t work_n = 0;
 };
 
 namespace {
 
 amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
-  if (!c) return fail(AMH_E_INVAL, "config is NULL");
-  if (c->L < 2 || c->L > 1024) return fail(AMH_E_INVAL, "L=%d outside [2, 1024]", c->L);
-  if (c->n_chains < 1) return fail(AMH_E_INVAL, "n_chains=%d < 1", c->n_chains);
-  if (c->n_bins < 4 || c->n_bins > 64) return fail(AMH_E_INVAL, "n_bins=%d outside [4, 64]", c->n_bins);
-  if (c->window_d < 0) return fail(AMH_E_INVAL, "window_d=%d < 0", c->window_d);
-  if (!std::isfinite(c->d_min)) return fail(AMH_E_INVAL, "d_min not finite");
-  if (!(c->bin_w > 0.0) || !std::isfinite(c->bin_w)) return fail(AMH_E_INVAL, "bin_w must be > 0");
-  if (c->global_every < 0) return fail(AMH_E_INVAL, "global_every=%d < 0", c->global_every);
-  if (c->anchor_every < 1) return fail(AMH_E_INVAL, "anchor_every=%d < 1", c->anchor_every);
-  if (!(c->sigma >= 0.0) || !std::isfinite(c->sigma)) return fail(AMH_E_INVAL, "sigma must be finite and >= 0");
+  if (!c) return sfail(AMH_E_INVAL, "config is NULL");
+  if (c->L < 2 || c->L > 1024) return sfail(AMH_E_INVAL, "L=%d outside [2, 1024]", c->L);
+  if (c->n_chains < 1) return sfail(AMH_E_INVAL, "n_chains=%d < 1", c->n_chains);
+  if (c->n_bins < 4 || c->n_bins > 64) return sfail(AMH_E_INVAL, "n_bins=%d outside [4, 64]", c->n_bins);
+  if (c->window_d < 0) return sfail(AMH_E_INVAL, "window_d=%d < 0", c->window_d);
+  if (!std::isfinite(c->d_min)) return sfail(AMH_E_INVAL, "d_min not finite");
+  if (!(c->bin_w > 0.0) || !std::isfinite(c->bin_w)) return sfail(AMH_E_INVAL, "bin_w must be > 0");
+  if (c->global_every < 0) return sfail(AMH_E_INVAL, "global_every=%d < 0", c->global_every);
+  if (c->anchor_every < 1) return sfail(AMH_E_INVAL, "anchor_every=%d < 1", c->anchor_every);
+  if (!(c->sigma >= 0.0) || !std::isfinite(c->sigma)) return sfail(AMH_E_INVAL, "sigma must be finite and >= 0");
   if (!(c->T0 > 0.0) || !(c->T1 > 0.0) || !std::isfinite(c->T0) || !std::isfinite(c->T1))
-    return fail(AMH_E_INVAL, "T0 and T1 must be finite and > 0");
+    return sfail(AMH_E_INVAL, "T0 and T1 must be finite and > 0");
   if (c->total_sweeps < 1 || c->total_sweeps > 0xFFFFFFFFLL)
-    return fail(AMH_E_INVAL, "total_sweeps=%lld outside [1, 2^32-1]", (long long)c->total_sweeps);
+    return sfail(AMH_E_INVAL, "total_sweeps=%lld outside [1, 2^32-1]", (long long)c->total_sweeps);
   if ((uint64_t)c->chain_offset + (uint64_t)c->n_chains > 0x100000000ULL)
-    return fail(AMH_E_INVAL, "chain_offset + n_chains exceeds 2^32");
+    return sfail(AMH_E_INVAL, "chain_offset + n_chains exceeds 2^32");
   int g = c->chains_per_group;
   if (g != 0 && g != 1 && g != 2 && g != 4)
-    return fail(AMH_E_INVAL, "chains_per_group=%d not in {0,1,2,4}", g);
+    return sfail(AMH_E_INVAL, "chains_per_group=%d not in {0,1,2,4}", g);
   int w = c->waves_per_group;
-  if (w < 0 || w > 8) return fail(AMH_E_INVAL, "waves_per_group=%d outside [0, 8]", w);
+  if (w < 0 || w > 8) return sfail(AMH_E_INVAL, "waves_per_group=%d outside [0, 8]", w);
   if (g == 0) {
     g = 4;
     while (g > 1 && ((size_t)c->n_chains < (size_t)g * 256 ||
@@ -98,10 +113,10 @@ amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
       g >>= 1;
   }
   if (w == 0) w = 2 * g > 4 ? 2 * g : 4;
-  if (w < g) return fail(AMH_E_INVAL, "waves_per_group=%d < chains_per_group=%d", w, g);
+  if (w < g) return sfail(AMH_E_INVAL, "waves_per_group=%d < chains_per_group=%d", w, g);
   const size_t need = amh::sweep_lds_bytes(g, c->L, w);
   if (need > kMaxLds)
-    return fail(AMH_E_INVAL, "L=%d with %d chains per workgroup needs %zu bytes of LDS (> %zu)",
+    return sfail(AMH_E_INVAL, "L=%d with %d chains per workgroup needs %zu bytes of LDS (> %zu)",
                 c->L, g, need, kMaxLds);
   *G = g;
   *W = w;
@@ -113,13 +128,14 @@ void free_ctx(amh_ctx* x) {
   if (!x) return;
   (void)hipFree(x->table); (void)hipFree(x->ydev); (void)hipFree(x->s); (void)hipFree(x->s_best); (void)hipFree(x->atoms);
   (void)hipFree(x->v); (void)hipFree(x->counters); (void)hipFree(x->err);
+  (void)hipFree(x->work);
   delete x;
 }
 
 template <typename T>
 amh_status dev_alloc(T** p, size_t count) {
   hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
-  if (e != hipSuccess) return fail(AMH_E_NOMEM, "hipMalloc(%zu bytes): %s", sizeof(T) * count, hipGetErrorString(e));
+  if (e != hipSuccess) return sfail(AMH_E_NOMEM, "hipMalloc(%zu bytes): %s", sizeof(T) * count, hipGetErrorString(e));
   return AMH_OK;
 }
 
@@ -145,90 +161,7 @@ amh_status launch_conf(const amh::ConfParams& P, int B, hipStream_t st) {
   return AMH_OK;
 }
 
-amh_status read_err(amh_ctx* x, unsigned int* out) {
-  HIP_OK(hipStreamSynchronize(x->stream));
-  HIP_OK(hipMemcpy(out, x->err, sizeof(unsigned int), hipMemcpyDeviceToHost));
-  return AMH_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-const char* amh_last_error(void) { return g_last_error.c_str(); }
-
-amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_dev, void* stream,
-                    amh_ctx** out) {
-  if (!out) return fail(AMH_E_INVAL, "out is NULL");
-  *out = nullptr;
-  int G = 0, W = 0;
-  size_t lds = 0;
-  amh_status st = validate(cfg, &G, &W, &lds);
-  if (st != AMH_OK) return st;
-  if (!y_dev) return fail(AMH_E_INVAL, "distogram table is NULL");
-  amh_ctx* x = new amh_ctx;
-  x->cfg = *cfg;
-  x->stream = reinterpret_cast<hipStream_t>(stream);
-  x->G = G;
-  x->W = W;
-  x->lds = lds;
-  const int L = cfg->L, C = cfg->n_chains, n = 2 * L;
-  const int64_t P = (int64_t)L * (L - 1) / 2;
-  x->stride = row_stride(cfg->n_bins);
-  if ((st = dev_alloc(&x->table, (size_t)P * x->stride)) != AMH_OK ||
-      (st = dev_alloc(&x->ydev, (size_t)(P + 1) * x->stride)) != AMH_OK ||
-      (st = dev_alloc(&x->s, (size_t)C * n)) != AMH_OK ||
-      (st = dev_alloc(&x->s_best, (size_t)C * n)) != AMH_OK ||
-      (st = dev_alloc(&x->atoms, (size_t)C * L * 12)) != AMH_OK ||
-      (st = dev_alloc(&x->v, (size_t)C * 2)) != AMH_OK ||
-      (st = dev_alloc(&x->counters, (size_t)C * 4)) != AMH_OK ||
-      (st = dev_alloc(&x->err, 1)) != AMH_OK) {
-    free_ctx(x);
-    return st;
-  }
-  hipError_t e = hipMemsetAsync(x->err, 0, sizeof(unsigned int), x->stream);
-  if (e == hipSuccess)   // row P of the deviation table is the zero row
-    e = hipMemsetAsync(x->ydev + (size_t)P * x->stride, 0, sizeof(float) * x->stride, x->stream);
-  if (e == hipSuccess) {
-    const int64_t work = P * x->stride;
-    int blocks = (int)((work + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(amh::ingest_kernel, dim3(blocks), dim3(256), 0, x->stream, y_dev, P,
-                       cfg->n_bins, x->stride, x->table, x->ydev, x->err);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && s0_dev)
-    e = hipMemcpyAsync(x->s, s0_dev, sizeof(double) * C * n, hipMemcpyDeviceToDevice, x->stream);
-  if (e != hipSuccess) {
-    free_ctx(x);
-    return fail(AMH_E_DEVICE, "amh_init: %s", hipGetErrorString(e));
-  }
-  amh::ConfParams cp = conf_base(x);
-  cp.s_in = s0_dev ? x->s : nullptr;
-  cp.s_out = s0_dev ? nullptr : x->s;
-  cp.atoms64_out = x->atoms;
-  cp.v_state = x->v;
-  cp.counters = x->counters;
-  cp.s_best = x->s_best;
-  if ((st = launch_conf(cp, C, x->stream)) != AMH_OK) { free_ctx(x); return st; }
-  unsigned int err = 0;
-  if ((st = read_err(x, &err)) != AMH_OK) { free_ctx(x); return st; }
-  if (err) {
-    free_ctx(x);
-    return fail(AMH_E_NUMERIC, (err & amh::kErrTable) ? "distogram table holds a non-finite entry"
-                                                       : "initial energy is not finite");
-  }
-  *out = x;
-  return AMH_OK;
-}
-
-amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
-  if (n_sweeps < 0) return fail(AMH_E_INVAL, "n_sweeps < 0");
-  if (x->t + n_sweeps > x->cfg.total_sweeps)
-    return fail(AMH_E_INVAL, "sweep %lld + %lld passes total_sweeps=%lld", (long long)x->t,
-                (long long)n_sweeps, (long long)x->cfg.total_sweeps);
-  if (n_sweeps == 0) return AMH_OK;
+amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   const amh_config& c = x->cfg;
   amh::SweepParams P{};
   P.table = x->table;
@@ -276,6 +209,95 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
   P.tr_anchor = x->tr_anchor;
   P.trace_anchor_cap = x->trace_anchor_cap;
   P.trace_anchor0 = x->trace_anchor0;
+  return P;
+}
+
+amh_status read_err(amh_ctx* x, unsigned int* out) {
+  HIP_OK(hipStreamSynchronize(x->stream));
+  HIP_OK(hipMemcpy(out, x->err, sizeof(unsigned int), hipMemcpyDeviceToHost));
+  return AMH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* amh_last_error(void) { return g_last_error.c_str(); }
+
+amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_dev, void* stream,
+                    amh_ctx** out) {
+  if (!out) return sfail(AMH_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int G = 0, W = 0;
+  size_t lds = 0;
+  amh_status st = validate(cfg, &G, &W, &lds);
+  if (st != AMH_OK) return st;
+  if (!y_dev) return sfail(AMH_E_INVAL, "distogram table is NULL");
+  amh_ctx* x = new amh_ctx;
+  x->cfg = *cfg;
+  x->stream = reinterpret_cast<hipStream_t>(stream);
+  x->G = G;
+  x->W = W;
+  x->lds = lds;
+  const int L = cfg->L, C = cfg->n_chains, n = 2 * L;
+  const int64_t P = (int64_t)L * (L - 1) / 2;
+  x->stride = row_stride(cfg->n_bins);
+  if ((st = dev_alloc(&x->table, (size_t)P * x->stride)) != AMH_OK ||
+      (st = dev_alloc(&x->ydev, (size_t)(P + 1) * x->stride)) != AMH_OK ||
+      (st = dev_alloc(&x->s, (size_t)C * n)) != AMH_OK ||
+      (st = dev_alloc(&x->s_best, (size_t)C * n)) != AMH_OK ||
+      (st = dev_alloc(&x->atoms, (size_t)C * L * 12)) != AMH_OK ||
+      (st = dev_alloc(&x->v, (size_t)C * 2)) != AMH_OK ||
+      (st = dev_alloc(&x->counters, (size_t)C * 4)) != AMH_OK ||
+      (st = dev_alloc(&x->err, 1)) != AMH_OK) {
+    free_ctx(x);
+    return st;
+  }
+  hipError_t e = hipMemsetAsync(x->err, 0, sizeof(unsigned int), x->stream);
+  if (e == hipSuccess)   // row P of the deviation table is the zero row
+    e = hipMemsetAsync(x->ydev + (size_t)P * x->stride, 0, sizeof(float) * x->stride, x->stream);
+  if (e == hipSuccess) {
+    const int64_t work = P * x->stride;
+    int blocks = (int)((work + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(amh::ingest_kernel, dim3(blocks), dim3(256), 0, x->stream, y_dev, P,
+                       cfg->n_bins, x->stride, x->table, x->ydev, x->err);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && s0_dev)
+    e = hipMemcpyAsync(x->s, s0_dev, sizeof(double) * C * n, hipMemcpyDeviceToDevice, x->stream);
+  if (e != hipSuccess) {
+    free_ctx(x);
+    return sfail(AMH_E_DEVICE, "amh_init: %s", hipGetErrorString(e));
+  }
+  amh::ConfParams cp = conf_base(x);
+  cp.s_in = s0_dev ? x->s : nullptr;
+  cp.s_out = s0_dev ? nullptr : x->s;
+  cp.atoms64_out = x->atoms;
+  cp.v_state = x->v;
+  cp.counters = x->counters;
+  cp.s_best = x->s_best;
+  if ((st = launch_conf(cp, C, x->stream)) != AMH_OK) { free_ctx(x); return st; }
+  unsigned int err = 0;
+  if ((st = read_err(x, &err)) != AMH_OK) { free_ctx(x); return st; }
+  if (err) {
+    free_ctx(x);
+    return sfail(AMH_E_NUMERIC, (err & amh::kErrTable) ? "distogram table holds a non-finite entry"
+                                                       : "initial energy is not finite");
+  }
+  *out = x;
+  return AMH_OK;
+}
+
+amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (n_sweeps < 0) return sfail(AMH_E_INVAL, "n_sweeps < 0");
+  if (x->t + n_sweeps > x->cfg.total_sweeps)
+    return sfail(AMH_E_INVAL, "sweep %lld + %lld passes total_sweeps=%lld", (long long)x->t,
+                (long long)n_sweeps, (long long)x->cfg.total_sweeps);
+  if (n_sweeps == 0) return AMH_OK;
+  const amh::SweepParams P = sweep_params(x, n_sweeps);
+  const amh_config& c = x->cfg;
   const dim3 grid((c.n_chains + x->G - 1) / x->G), block(64 * x->W);
   switch (x->G) {
     case 1:
@@ -301,14 +323,14 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
 
 amh_status amh_energy(amh_ctx* x, const double* s_in_dev, int32_t B, int32_t which,
                       double* V_out_dev, double* s_out_dev, float* cb_out_dev) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
-  if (B < 0) return fail(AMH_E_INVAL, "B < 0");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (B < 0) return sfail(AMH_E_INVAL, "B < 0");
   amh::ConfParams P = conf_base(x);
   if (s_in_dev) {
     P.s_in = s_in_dev;
   } else {
-    if (B != x->cfg.n_chains) return fail(AMH_E_INVAL, "B=%d must equal n_chains=%d", B, x->cfg.n_chains);
-    if (which != 0 && which != 1) return fail(AMH_E_INVAL, "which=%d not in {0, 1}", which);
+    if (B != x->cfg.n_chains) return sfail(AMH_E_INVAL, "B=%d must equal n_chains=%d", B, x->cfg.n_chains);
+    if (which != 0 && which != 1) return sfail(AMH_E_INVAL, "which=%d not in {0, 1}", which);
     P.s_in = which == 0 ? x->s : x->s_best;
   }
   P.V_out = V_out_dev;
@@ -319,8 +341,8 @@ amh_status amh_energy(amh_ctx* x, const double* s_in_dev, int32_t B, int32_t whi
 
 amh_status amh_conformation(const double* s_dev, int32_t B, int32_t L, float* atoms_out_dev,
                             void* stream) {
-  if (!s_dev || !atoms_out_dev) return fail(AMH_E_INVAL, "NULL pointer");
-  if (B < 0 || L < 2 || L > 1024) return fail(AMH_E_INVAL, "B=%d, L=%d out of range", B, L);
+  if (!s_dev || !atoms_out_dev) return sfail(AMH_E_INVAL, "NULL pointer");
+  if (B < 0 || L < 2 || L > 1024) return sfail(AMH_E_INVAL, "B=%d, L=%d out of range", B, L);
   amh::ConfParams P{};
   P.L = L;
   P.s_in = s_dev;
@@ -330,7 +352,7 @@ amh_status amh_conformation(const double* s_dev, int32_t B, int32_t L, float* at
 
 amh_status amh_get_state(amh_ctx* x, double* s_dev, double* s_best_dev, double* v_dev,
                          int64_t* counters_dev, double* atoms_dev, int64_t* t_out) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
   const size_t C = x->cfg.n_chains, n = 2 * (size_t)x->cfg.L;
   const auto D2D = hipMemcpyDeviceToDevice;
   if (s_dev) HIP_OK(hipMemcpyAsync(s_dev, x->s, sizeof(double) * C * n, D2D, x->stream));
@@ -345,8 +367,8 @@ amh_status amh_get_state(amh_ctx* x, double* s_dev, double* s_best_dev, double* 
 amh_status amh_set_state(amh_ctx* x, const double* s_dev, const double* s_best_dev,
                          const double* v_dev, const int64_t* counters_dev, const double* atoms_dev,
                          int64_t t) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
-  if (t < 0 || t > x->cfg.total_sweeps) return fail(AMH_E_INVAL, "t=%lld out of range", (long long)t);
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (t < 0 || t > x->cfg.total_sweeps) return sfail(AMH_E_INVAL, "t=%lld out of range", (long long)t);
   const size_t C = x->cfg.n_chains, n = 2 * (size_t)x->cfg.L;
   const auto D2D = hipMemcpyDeviceToDevice;
   if (s_dev) HIP_OK(hipMemcpyAsync(x->s, s_dev, sizeof(double) * C * n, D2D, x->stream));
@@ -368,8 +390,8 @@ amh_status amh_set_state(amh_ctx* x, const double* s_dev, const double* s_best_d
 }
 
 amh_status amh_set_target(amh_ctx* x, double target) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
-  if (std::isnan(target)) return fail(AMH_E_INVAL, "target is NaN");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (std::isnan(target)) return sfail(AMH_E_INVAL, "target is NaN");
   x->target = target;
   return AMH_OK;
 }
@@ -377,15 +399,15 @@ amh_status amh_set_target(amh_ctx* x, double target) {
 amh_status amh_set_trace(amh_ctx* x, int32_t n, const int32_t* chain_ids, double* dE_dev,
                          double* delta_dev, uint8_t* acc_dev, int64_t capacity, double* anchor_dev,
                          int64_t anchor_capacity) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
-  if (n < 0 || n > 4) return fail(AMH_E_INVAL, "n=%d outside [0, 4]", n);
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (n < 0 || n > 4) return sfail(AMH_E_INVAL, "n=%d outside [0, 4]", n);
   if (n > 0 && (!chain_ids || !dE_dev || !delta_dev || !acc_dev || capacity < 0 || anchor_capacity < 0 ||
                 (anchor_capacity > 0 && !anchor_dev)))
-    return fail(AMH_E_INVAL, "trace buffers missing");
+    return sfail(AMH_E_INVAL, "trace buffers missing");
   for (int m = 0; m < 4; ++m) {
     x->trace_chain[m] = (m < n) ? chain_ids[m] : -1;
     if (m < n && (chain_ids[m] < -1 || chain_ids[m] >= x->cfg.n_chains))
-      return fail(AMH_E_INVAL, "trace chain %d out of range", chain_ids[m]);
+      return sfail(AMH_E_INVAL, "trace chain %d out of range", chain_ids[m]);
   }
   x->n_trace = n;
   x->tr_dE = dE_dev;
@@ -400,17 +422,17 @@ amh_status amh_set_trace(amh_ctx* x, int32_t n, const int32_t* chain_ids, double
 }
 
 amh_status amh_poll(amh_ctx* x) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
   unsigned int err = 0;
   amh_status st = read_err(x, &err);
   if (st != AMH_OK) return st;
-  if (err & amh::kErrStall) return fail(AMH_E_DEVICE, "a pipelined localized sweep exceeded its wait bound");
-  if (err) return fail(AMH_E_NUMERIC, "non-finite %s", (err & amh::kErrTable) ? "table entry" : "energy");
+  if (err & amh::kErrStall) return sfail(AMH_E_DEVICE, "a pipelined localized sweep exceeded its wait bound");
+  if (err) return sfail(AMH_E_NUMERIC, "non-finite %s", (err & amh::kErrTable) ? "table entry" : "energy");
   return AMH_OK;
 }
 
 amh_status amh_info(amh_ctx* x, int32_t* G, int32_t* W, int32_t* lds, int64_t* t) {
-  if (!x) return fail(AMH_E_INVAL, "ctx is NULL");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
   if (G) *G = x->G;
   if (W) *W = x->W;
   if (lds) *lds = (int32_t)x->lds;
@@ -420,7 +442,7 @@ amh_status amh_info(amh_ctx* x, int32_t* G, int32_t* W, int32_t* lds, int64_t* t
 
 amh_status amh_philox(const uint32_t* ctr_dev, int64_t n, uint64_t key, uint32_t* out_dev,
                       void* stream) {
-  if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) return fail(AMH_E_INVAL, "bad philox arguments");
+  if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) return sfail(AMH_E_INVAL, "bad philox arguments");
   if (n == 0) return AMH_OK;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
@@ -432,19 +454,343 @@ amh_status amh_philox(const uint32_t* ctr_dev, int64_t n, uint64_t key, uint32_t
 }
 
 amh_status amh_grad(amh_ctx* x, const double* s_dev, int32_t B, double* V_out_dev, double* g_out_dev) {
-  (void)x; (void)s_dev; (void)B; (void)V_out_dev; (void)g_out_dev;
-  return fail(AMH_E_UNSUPPORTED, "amh_grad is not provided by this build");
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (B < 0) return sfail(AMH_E_INVAL, "B < 0");
+  if (!s_dev && B != x->cfg.n_chains)
+    return sfail(AMH_E_INVAL, "B=%d must equal n_chains=%d when s is NULL", B, x->cfg.n_chains);
+  if (!V_out_dev && !g_out_dev) return sfail(AMH_E_INVAL, "V_out and g_out are both NULL");
+  if (B == 0) return AMH_OK;
+  amh::GradParams P{};
+  P.L = x->cfg.L;
+  P.s = s_dev ? s_dev : x->s;
+  P.table = x->table;
+  P.stride = x->stride;
+  P.nb = x->cfg.n_bins;
+  P.d_min = x->cfg.d_min;
+  P.bin_w = x->cfg.bin_w;
+  P.V = V_out_dev;
+  P.g = g_out_dev;
+  P.err = x->err;
+  const size_t lds = amh::grad_lds_bytes(P.L, amh::kGradThreads / 64);
+  if (lds > kMaxLds) return sfail(AMH_E_INVAL, "L=%d needs %zu bytes of LDS for the gradient", P.L, lds);
+  HIP_OK(hipFuncSetAttribute((const void*)amh::grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL(amh::grad_kernel, dim3(B), dim3(amh::kGradThreads), lds, x->stream, P);
+  HIP_OK(hipGetLastError());
+  return AMH_OK;
 }
 
-amh_status amh_submit(void* server, const void* job, uint64_t* job_id) {
-  (void)server; (void)job; (void)job_id;
-  return fail(AMH_E_UNSUPPORTED, "amh_submit is not provided by this build");
+amh_status amh_minimize(amh_ctx* x, double* s_dev, int32_t B, const amh_lbfgs_opts* o,
+                        double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
+                        double* f_trace_dev, double* x_trace_dev) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (!o) return sfail(AMH_E_INVAL, "opts is NULL");
+  if (B < 0) return sfail(AMH_E_INVAL, "B < 0");
+  if (!s_dev && B != x->cfg.n_chains)
+    return sfail(AMH_E_INVAL, "B=%d must equal n_chains=%d when s is NULL", B, x->cfg.n_chains);
+  if (o->n_iter < 0) return sfail(AMH_E_INVAL, "n_iter=%d < 0", o->n_iter);
+  if (o->m < 1 || o->m > amh::kLbfgsMaxHistory)
+    return sfail(AMH_E_INVAL, "m=%d outside [1, %d]", o->m, amh::kLbfgsMaxHistory);
+  if (o->nonmonotone < 1 || o->nonmonotone > amh::kLbfgsMaxNonmonotone)
+    return sfail(AMH_E_INVAL, "nonmonotone=%d outside [1, %d]", o->nonmonotone, amh::kLbfgsMaxNonmonotone);
+  if (o->max_ls < 1) return sfail(AMH_E_INVAL, "max_ls=%d < 1", o->max_ls);
+  if (!(o->c1 > 0.0 && o->c1 < 1.0)) return sfail(AMH_E_INVAL, "c1 must lie in (0, 1)");
+  if (!(o->shrink > 0.0 && o->shrink < 1.0)) return sfail(AMH_E_INVAL, "shrink must lie in (0, 1)");
+  if (!(o->gtol >= 0.0) || !std::isfinite(o->gtol)) return sfail(AMH_E_INVAL, "gtol must be finite and >= 0");
+  if (!(o->step0 > 0.0) || !std::isfinite(o->step0)) return sfail(AMH_E_INVAL, "step0 must be finite and > 0");
+  if (B == 0) return AMH_OK;
+  const int L = x->cfg.L;
+  const size_t need = amh::lbfgs_work_doubles(L, o->m) * (size_t)B;
+  if (need > x->work_n) {
+    HIP_OK(hipStreamSynchronize(x->stream));
+    (void)hipFree(x->work);
+    x->work = nullptr;
+    x->work_n = 0;
+    amh_status st = dev_alloc(&x->work, need);
+    if (st != AMH_OK) return st;
+    x->work_n = need;
+  }
+  amh::LbfgsParams P{};
+  P.L = L;
+  P.s = s_dev ? s_dev : x->s;
+  P.table = x->table;
+  P.stride = x->stride;
+  P.nb = x->cfg.n_bins;
+  P.d_min = x->cfg.d_min;
+  P.bin_w = x->cfg.bin_w;
+  P.n_iter = o->n_iter;
+  P.m = o->m;
+  P.nonmonotone = o->nonmonotone;
+  P.max_ls = o->max_ls;
+  P.c1 = o->c1;
+  P.shrink = o->shrink;
+  P.gtol = o->gtol;
+  P.step0 = o->step0;
+  P.work = x->work;
+  P.V = V_out_dev;
+  P.iters = iters_out_dev;
+  P.status = status_out_dev;
+  P.f_trace = f_trace_dev;
+  P.x_trace = x_trace_dev;
+  P.err = x->err;
+  if (!s_dev) {   // the context's chains: keep V, the best state and the coordinates current
+    P.v_state = x->v;
+    P.s_best = x->s_best;
+  }
+  const size_t lds = amh::lbfgs_lds_bytes(L, amh::kGradThreads / 64, o->m, o->nonmonotone);
+  if (lds > kMaxLds) return sfail(AMH_E_INVAL, "L=%d needs %zu bytes of LDS for L-BFGS", L, lds);
+  HIP_OK(hipFuncSetAttribute((const void*)amh::lbfgs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL(amh::lbfgs_kernel, dim3(B), dim3(amh::kGradThreads), lds, x->stream, P);
+  HIP_OK(hipGetLastError());
+  if (!s_dev) {
+    amh::ConfParams cp{};
+    cp.L = L;
+    cp.s_in = x->s;
+    cp.atoms64_out = x->atoms;
+    return launch_conf(cp, B, x->stream);
+  }
+  return AMH_OK;
 }
 
 amh_status amh_destroy(amh_ctx* x) {
   if (!x) return AMH_OK;
   (void)hipStreamSynchronize(x->stream);
   free_ctx(x);
+  return AMH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: several contexts (proteins of different lengths) advanced by one launch
+// per launch shape.
+
+namespace {
+
+constexpr int kRing = 8;   // pinned descriptor staging buffers in flight
+// launch plans: 0 = each context's own shape, then uniform (chains per group, waves)
+constexpr int kPlans = 6;
+constexpr int kPlanShape[kPlans][2] = {{0, 0}, {1, 4}, {2, 4}, {2, 8}, {4, 4}, {4, 8}};
+
+}  // namespace
+
+struct amh_batch {
+  std::vector<amh_ctx*> m;
+  hipStream_t stream = nullptr;
+  int plan = 0;
+  struct Launch {
+    int G = 1, W = 4;
+    size_t lds = 0;
+    int n_wg = 0;
+    int2* d_map = nullptr;
+  };
+  std::vector<Launch> launches;
+  amh::SweepParams* d_desc = nullptr;
+  amh::SweepParams* h_desc[kRing] = {};
+  hipEvent_t ev[kRing] = {};
+  bool ev_used[kRing] = {};
+  int ring = 0;
+};
+
+namespace {
+
+void free_launches(amh_batch* b) {
+  for (auto& l : b->launches) (void)hipFree(l.d_map);
+  b->launches.clear();
+}
+
+void free_batch(amh_batch* b) {
+  if (!b) return;
+  free_launches(b);
+  (void)hipFree(b->d_desc);
+  for (int i = 0; i < kRing; ++i) {
+    if (b->h_desc[i]) (void)hipHostFree(b->h_desc[i]);
+    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+  }
+  delete b;
+}
+
+void member_shape(const amh_ctx* x, int plan, int* G, int* W) {
+  if (plan == 0) { *G = x->G; *W = x->W; return; }
+  int g = kPlanShape[plan][0], w = kPlanShape[plan][1];
+  while (g > 1 && amh::sweep_lds_bytes(g, x->cfg.L, w) > kMaxLds) g >>= 1;
+  *G = g;
+  *W = w;
+}
+
+// Work of one chain group per sweep, in pair evaluations (orders the grid only).
+double member_cost(const amh_ctx* x) {
+  const double L = x->cfg.L, h = x->cfg.window_d / 2;
+  const int ge = x->cfg.global_every;
+  const double global = ge > 0 ? L * L * L / 3.0 / ge : 0.0;
+  const double local = 2.0 * L * h * (h + 1) * (ge > 0 ? 1.0 - 1.0 / ge : 1.0);
+  return global + local;
+}
+
+amh_status build_launches(amh_batch* b, int plan) {
+  HIP_OK(hipStreamSynchronize(b->stream));
+  free_launches(b);
+  std::vector<std::pair<int, int>> shapes;
+  std::vector<int> shape_of(b->m.size());
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    int G, W;
+    member_shape(b->m[i], plan, &G, &W);
+    auto it = std::find(shapes.begin(), shapes.end(), std::make_pair(G, W));
+    shape_of[i] = (int)(it - shapes.begin());
+    if (it == shapes.end()) shapes.emplace_back(G, W);
+  }
+  for (size_t s = 0; s < shapes.size(); ++s) {
+    amh_batch::Launch l;
+    l.G = shapes[s].first;
+    l.W = shapes[s].second;
+    std::vector<std::pair<double, int2>> items;
+    for (size_t i = 0; i < b->m.size(); ++i) {
+      if (shape_of[i] != (int)s) continue;
+      const amh_ctx* x = b->m[i];
+      l.lds = std::max(l.lds, amh::sweep_lds_bytes(l.G, x->cfg.L, l.W));
+      const int groups = (x->cfg.n_chains + l.G - 1) / l.G;
+      for (int g = 0; g < groups; ++g) items.push_back({member_cost(x), make_int2((int)i, g)});
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const auto& a, const auto& c) { return a.first > c.first; });
+    std::vector<int2> map;
+    for (auto& it : items) map.push_back(it.second);
+    l.n_wg = (int)map.size();
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&l.d_map), sizeof(int2) * map.size());
+    if (e != hipSuccess) return sfail(AMH_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    b->launches.push_back(l);
+    HIP_OK(hipMemcpy(l.d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice));
+  }
+  b->plan = plan;
+  return AMH_OK;
+}
+
+template <int G>
+amh_status launch_batch(const amh_batch* b, const amh_batch::Launch& l) {
+  HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_batch_kernel<G>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)l.lds));
+  hipLaunchKernelGGL(amh::sweep_batch_kernel<G>, dim3(l.n_wg), dim3(64 * l.W), l.lds, b->stream,
+                     (const amh::SweepParams*)b->d_desc, (const int2*)l.d_map);
+  HIP_OK(hipGetLastError());
+  return AMH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amh_status amh_batch_create(amh_ctx* const* ctxs, int32_t n, amh_batch** out) {
+  if (!out) return sfail(AMH_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctxs || n < 1) return sfail(AMH_E_INVAL, "need at least one context");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return sfail(AMH_E_INVAL, "context %d is NULL", i);
+    if (ctxs[i]->stream != ctxs[0]->stream)
+      return sfail(AMH_E_INVAL, "context %d is on another stream than context 0", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return sfail(AMH_E_INVAL, "context %d appears twice", i);
+  }
+  amh_batch* b = new amh_batch;
+  b->m.assign(ctxs, ctxs + n);
+  b->stream = ctxs[0]->stream;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_desc), sizeof(amh::SweepParams) * n);
+  for (int i = 0; e == hipSuccess && i < kRing; ++i) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc[i]), sizeof(amh::SweepParams) * n);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    free_batch(b);
+    return sfail(AMH_E_NOMEM, "amh_batch_create: %s", hipGetErrorString(e));
+  }
+  amh_status st = build_launches(b, 0);
+  if (st != AMH_OK) { free_batch(b); return st; }
+  *out = b;
+  return AMH_OK;
+}
+
+amh_status amh_batch_sweep(amh_batch* b, int64_t n_sweeps) {
+  if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
+  if (n_sweeps < 0) return sfail(AMH_E_INVAL, "n_sweeps < 0");
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    const amh_ctx* x = b->m[i];
+    if (x->t + n_sweeps > x->cfg.total_sweeps)
+      return sfail(AMH_E_INVAL, "member %zu: sweep %lld + %lld passes total_sweeps=%lld", i,
+                  (long long)x->t, (long long)n_sweeps, (long long)x->cfg.total_sweeps);
+  }
+  if (n_sweeps == 0) return AMH_OK;
+  const int slot = b->ring;
+  if (b->ev_used[slot]) HIP_OK(hipEventSynchronize(b->ev[slot]));
+  for (size_t i = 0; i < b->m.size(); ++i) b->h_desc[slot][i] = sweep_params(b->m[i], n_sweeps);
+  HIP_OK(hipMemcpyAsync(b->d_desc, b->h_desc[slot], sizeof(amh::SweepParams) * b->m.size(),
+                        hipMemcpyHostToDevice, b->stream));
+  HIP_OK(hipEventRecord(b->ev[slot], b->stream));
+  b->ev_used[slot] = true;
+  b->ring = (slot + 1) % kRing;
+  for (const auto& l : b->launches) {
+    amh_status st = l.G == 1 ? launch_batch<1>(b, l) : l.G == 2 ? launch_batch<2>(b, l) : launch_batch<4>(b, l);
+    if (st != AMH_OK) return st;
+  }
+  for (auto* x : b->m) x->t += n_sweeps;
+  return AMH_OK;
+}
+
+amh_status amh_batch_tune(amh_batch* b, int64_t sweeps_per_trial, float* ms_out, int32_t* plan_out) {
+  if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
+  if (sweeps_per_trial < 1) return sfail(AMH_E_INVAL, "sweeps_per_trial < 1");
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    const amh_ctx* x = b->m[i];
+    if (x->t + kPlans * sweeps_per_trial > x->cfg.total_sweeps)
+      return sfail(AMH_E_INVAL, "member %zu has fewer than %lld sweeps left for tuning", i,
+                  (long long)(kPlans * sweeps_per_trial));
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.0f;
+  amh_status st = AMH_OK;
+  for (int p = 0; p < kPlans && st == AMH_OK; ++p) {
+    if ((st = build_launches(b, p)) != AMH_OK) break;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) { st = sfail(AMH_E_DEVICE, "hipEventRecord"); break; }
+    if ((st = amh_batch_sweep(b, sweeps_per_trial)) != AMH_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = sfail(AMH_E_DEVICE, "timing a tuning trial failed");
+      break;
+    }
+    if (ms_out) ms_out[p] = ms;
+    if (p == 0 || ms < best_ms) { best = p; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != AMH_OK) return st;
+  if ((st = build_launches(b, best)) != AMH_OK) return st;
+  if (plan_out) *plan_out = best;
+  return AMH_OK;
+}
+
+amh_status amh_batch_set_plan(amh_batch* b, int32_t plan) {
+  if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
+  if (plan < 0 || plan >= kPlans) return sfail(AMH_E_INVAL, "plan=%d outside [0, %d)", plan, kPlans);
+  return build_launches(b, plan);
+}
+
+amh_status amh_batch_info(const amh_batch* b, int32_t* plan, int32_t* n_launches, int32_t* workgroups) {
+  if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
+  int wg = 0;
+  for (const auto& l : b->launches) wg += l.n_wg;
+  if (plan) *plan = b->plan;
+  if (n_launches) *n_launches = (int)b->launches.size();
+  if (workgroups) *workgroups = wg;
+  return AMH_OK;
+}
+
+amh_status amh_batch_destroy(amh_batch* b) {
+  if (!b) return AMH_OK;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
   return AMH_OK;
 }
 

@@ -74,5 +74,7 @@ __global__ void conf_energy_kernel(ConfParams P);
 __global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
 template <int G>
 __global__ void sweep_kernel(SweepParams P);
+template <int G>
+__global__ void sweep_batch_kernel(const SweepParams* descs, const int2* map);
 
 }  // namespace amh

@@ -37,11 +37,10 @@
 #include <stdint.h>
 
 #include "amh_device.h"
+#include "amh_geom.h"
 #include "amh_kernels.h"
 
 namespace amh {
-
-constexpr double kDeg = kPi / 180.0;
 
 // ---------------------------------------------------------------------------
 // Table ingest: repack [P][nb] rows into padded rows [y1, y0..y_{nb-1}, y_{nb-2}, 0...]
@@ -73,60 +72,6 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
     const U4 c{ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
     const U4 r = philox10(c, k0, k1);
     out[4 * i] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
-  }
-}
-
-__device__ __forceinline__ double* atom(double* x64, int r, int a) { return x64 + (4 * r + a) * 3; }
-__device__ __forceinline__ const double* atom(const double* x64, int r, int a) {
-  return x64 + (4 * r + a) * 3;
-}
-
-// ---------------------------------------------------------------------------
-// Serial float64 NeRF of one chain, executed in lockstep by a whole wavefront (all
-// lanes hold the same values; the torsion cosines and sines are computed 64 at a
-// time, one per lane).  Lane 0 writes the float64 atoms x64 [L][4][3].
-__device__ void nerf_chain(const double* __restrict__ s, int L, double* __restrict__ x64, int lane) {
-  const double ct_cacn = cos(kAngCACN * kDeg), st_cacn = sin(kAngCACN * kDeg);
-  const double ct_cnca = cos(kAngCNCA * kDeg), st_cnca = sin(kAngCNCA * kDeg);
-  const double ct_ncac = cos(kAngNCAC * kDeg), st_ncac = sin(kAngNCAC * kDeg);
-  const double ct_ncacb = cos(kAngNCACB * kDeg), st_ncacb = sin(kAngNCACB * kDeg);
-  const double co = cos(kTorOmega * kDeg), so = sin(kTorOmega * kDeg);
-  const double ccb = cos(kTorCB * kDeg), scb = sin(kTorCB * kDeg);
-  double N[3] = {0.0, 0.0, 0.0};
-  double CA[3] = {kBondNCA, 0.0, 0.0};
-  double C[3] = {kBondNCA - kBondCAC * ct_ncac, kBondCAC * st_ncac, 0.0};
-  const int n = 2 * L;
-  double cs = 1.0, sn = 0.0;
-  {
-    const double a = lane < n ? s[lane] : 0.0;
-    sincos(a, &sn, &cs);
-  }
-  for (int c = 0; c < L; ++c) {
-    if (c > 0) {
-      const int m0 = 2 * c - 1, m1 = 2 * c;   // psi_{c-1}, phi_c
-      const double cpsi = readlane_d(cs, m0 & 63), spsi = readlane_d(sn, m0 & 63);
-      if ((m1 & 63) == 0) {
-        const int m = m1 + lane;
-        const double a = m < n ? s[m] : 0.0;
-        sincos(a, &sn, &cs);
-      }
-      const double cphi = readlane_d(cs, m1 & 63), sphi = readlane_d(sn, m1 & 63);
-      double Nn[3], CAn[3], Cn[3];
-      nerf_place(N, CA, C, kBondCN, ct_cacn, st_cacn, cpsi, spsi, Nn);
-      nerf_place(CA, C, Nn, kBondNCA, ct_cnca, st_cnca, co, so, CAn);
-      nerf_place(C, Nn, CAn, kBondCAC, ct_ncac, st_ncac, cphi, sphi, Cn);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { N[a] = Nn[a]; CA[a] = CAn[a]; C[a] = Cn[a]; }
-    }
-    double B[3];
-    nerf_place(C, N, CA, kBondCACB, ct_ncacb, st_ncacb, ccb, scb, B);
-    if (lane == 0) {
-      double* o = atom(x64, c, 0);
-      o[0] = N[0]; o[1] = N[1]; o[2] = N[2];
-      o[3] = CA[0]; o[4] = CA[1]; o[5] = CA[2];
-      o[6] = C[0]; o[7] = C[1]; o[8] = C[2];
-      o[9] = B[0]; o[10] = B[1]; o[11] = B[2];
-    }
   }
 }
 
@@ -439,12 +384,14 @@ __device__ __forceinline__ void add_chain(double* acc, int g, double v) {
     if (q == g) acc[q] += v;
 }
 
+// The sweeps of one workgroup: chains group*G .. group*G + G-1 of the protein that P
+// describes, over sweeps [P.t0, P.t0 + P.n_sweeps).
 template <int G>
-__global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
+__device__ __forceinline__ void sweep_body(const SweepParams& P, const int group) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int tid = threadIdx.x, T = blockDim.x, wave = tid >> 6, lane = tid & 63, W = T >> 6;
   const int L = P.L, n = 2 * L;
-  const int c0 = blockIdx.x * G;
+  const int c0 = group * G;
   const int nact = P.C - c0 < G ? P.C - c0 : G;
   const Lds S{lds, L, G};
   const Spline32 sp{P.inv_w, P.off, P.tmax};
@@ -519,7 +466,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
 #pragma unroll
       for (int g = 0; g < G; ++g) Rp[g] = 0.0;
       Batch bt{};
-      D3 nA{0, 0, 0}, nB{0, 0, 0}, nU{0, 0, 1};   // owner: pivot bond of proposal k+1
+      D3 nA{0, 0, 0}, nU{0, 0, 1};   // owner: pivot point and axis of proposal k+1
       if (owner) {
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
         D3 a, b;
@@ -541,6 +488,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
           S.w32(g)[r] = make_float4((float)(x.x - R.a[0]), (float)(x.y - R.a[1]), (float)(x.z - R.a[2]), 0.0f);
         }
         if (owner && k + 1 < n) {
+          D3 nB;
           axis_atoms(S.x64(wave), k + 1, nA, nB);
           nU = unit(nA, nB);
         }
@@ -577,29 +525,39 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
             float4 py = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float pf = 0.0f;
             int pg = 0;
-#pragma unroll 2
-            for (int i = ib; i < ie; ++i) {
-              float d2[G];
+            // NR rows per step: the NR * G broadcast reads are issued together, the
+            // distance test is branch-free and one branch covers the NR rows
+            constexpr int NR = G >= 4 ? 2 : 4;
+            for (int i0 = ib; i0 < ie; i0 += NR) {
+              float d2[NR][G];
               bool any = false;
 #pragma unroll
-              for (int g = 0; g < G; ++g) {
-                const float4 xi = S.w32(g)[i];
-                const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
-                d2[g] = dx * dx + dy * dy + dz * dz;
-                any |= d2[g] < P.d2far;
-              }
-              if (any) {
-                const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
+              for (int u = 0; u < NR; ++u) {
+                const int i = i0 + u < ie ? i0 + u : ie - 1;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                  if (d2[g] < P.d2far) {
-                    if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
-                    int b;
-                    spline_pos(__builtin_amdgcn_sqrtf(d2[g]), sp, b, pf);
-                    const float* q = row + b;
-                    py = make_float4(q[0], q[1], q[2], q[3]);
-                    pg = g;
-                    pend = true;
+                  const float4 xi = S.w32(g)[i];
+                  const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
+                  const float q = dx * dx + dy * dy + dz * dz;
+                  d2[u][g] = i0 + u < ie ? q : 3.0e38f;
+                  any |= d2[u][g] < P.d2far;
+                }
+              }
+              if (any) {
+#pragma unroll
+                for (int u = 0; u < NR; ++u) {
+                  const float* row = P.ydev + (size_t)pair_row(i0 + u, j, L) * P.stride;
+#pragma unroll
+                  for (int g = 0; g < G; ++g) {
+                    if (d2[u][g] < P.d2far) {
+                      if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
+                      int b;
+                      spline_pos(__builtin_amdgcn_sqrtf(d2[u][g]), sp, b, pf);
+                      const float* q = row + b;
+                      py = make_float4(q[0], q[1], q[2], q[3]);
+                      pg = g;
+                      pend = true;
+                    }
                   }
                 }
               }
@@ -734,8 +692,25 @@ __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
   }
 }
 
+template <int G>
+__global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
+  sweep_body<G>(P, blockIdx.x);
+}
+
+// Several proteins in one launch: workgroup b runs chain group map[b].y of the
+// protein described by descs[map[b].x] (the grid is ordered by decreasing work).
+template <int G>
+__global__ __launch_bounds__(512) void sweep_batch_kernel(const SweepParams* __restrict__ descs,
+                                                          const int2* __restrict__ map) {
+  const int2 wm = map[blockIdx.x];
+  sweep_body<G>(descs[wm.x], wm.y);
+}
+
 template __global__ void sweep_kernel<1>(SweepParams);
 template __global__ void sweep_kernel<2>(SweepParams);
 template __global__ void sweep_kernel<4>(SweepParams);
+template __global__ void sweep_batch_kernel<1>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<2>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<4>(const SweepParams*, const int2*);
 
 }  // namespace amh

@@ -189,3 +189,13 @@ def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process with the given mean rate."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def batch_workloads(n: int = 64, lo: int = 50, hi: int = 600, chains: int = 256,
+                    sweeps: int = 5000, seed: int = 0x414D4803) -> list[Workload]:
+    """Ragged batch of proteins (lengths uniform on [lo, hi]), each with its own
+    protein/noise seeds and its own Philox key, window 12, global every 10 sweeps."""
+    Ls = batch_lengths(n, lo, hi, seed)
+    return [Workload(f"batch{i:02d}-L{int(L)}", L=int(L), n_chains=chains, total_sweeps=sweeps,
+                     window_d=12, seed=(seed << 16) + i, protein_seed=1000 + i,
+                     noise_seed=2000 + i) for i, L in enumerate(Ls)]

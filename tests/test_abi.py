@@ -77,10 +77,39 @@ def test_null_arguments_rejected(amh):
     assert amh.lib().amh_destroy(None) == amh.OK
     assert amh.lib().amh_conformation(None, 1, 10, None, None) == amh.E_INVAL
     assert amh.lib().amh_philox(None, 4, 0, None, None) == amh.E_INVAL
+    assert amh.lib().amh_grad(None, None, 1, None, None) == amh.E_INVAL
+    opts = amh.lbfgs_opts()
+    assert amh.lib().amh_minimize(None, None, 1, C.byref(opts), None, None, None, None, None) == amh.E_INVAL
 
 
-def test_unprovided_calls_report_unsupported(amh):
-    assert amh.lib().amh_submit(None, None, None) == amh.E_UNSUPPORTED
+def test_lbfgs_opts_layout(amh):
+    assert C.sizeof(amh.LbfgsOpts) == 48 and amh.LbfgsOpts.c1.offset == 16
+
+
+def test_server_calls_reject_null_arguments(amh):
+    assert amh.lib().amh_submit(None, None, None) == amh.E_INVAL
+    h = C.c_void_p()
+    assert amh.lib().amh_server_create(None, None, C.byref(h)) == amh.E_INVAL
+    for bad in (dict(hbm_budget_bytes=0), dict(max_active=0), dict(sweeps_per_round=0), dict(plan=6)):
+        o = amh.ServerOpts(hbm_budget_bytes=1 << 30, max_active=4, sweeps_per_round=10, plan=0)
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert amh.lib().amh_server_create(C.byref(o), None, C.byref(h)) == amh.E_INVAL
+    assert amh.lib().amh_server_step(None, None, None) == amh.E_INVAL
+    st = amh.JobStatus()
+    assert amh.lib().amh_server_job(None, 1, C.byref(st), None, None) == amh.E_INVAL
+    assert amh.lib().amh_server_destroy(None) == amh.OK
+    arr = (C.c_void_p * 1)(None)
+    assert amh.lib().amh_batch_create(arr, 1, C.byref(h)) == amh.E_INVAL
+    assert amh.lib().amh_batch_create(arr, 0, C.byref(h)) == amh.E_INVAL
+    assert amh.lib().amh_batch_sweep(None, 1) == amh.E_INVAL
+    assert amh.lib().amh_batch_destroy(None) == amh.OK
+
+
+def test_server_struct_layouts(amh):
+    assert C.sizeof(amh.ServerOpts) == 24
+    assert C.sizeof(amh.Job) == 96 + 8 + 8 and amh.Job.target.offset == 104
+    assert C.sizeof(amh.JobStatus) == 72 and amh.JobStatus.best_V.offset == 24
 
 
 def test_missing_library_fails_loudly(amh, monkeypatch, tmp_path):

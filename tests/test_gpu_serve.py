@@ -1,0 +1,123 @@
+"""The continuous-batching server (amh_server_* / amh_submit).
+
+Each job's result must be the same alone and in the mix: the best states and
+per-chain energies of jobs served together (admitted as memory frees up, their
+sweeps sharing launches) are compared bit for bit with the same jobs served one
+at a time.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as sy
+
+pytestmark = pytest.mark.gpu
+
+gu = pytest.importorskip("gpu_util")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _jobs():
+    from paper_2211_03193_amd import amh
+    rng = np.random.default_rng(5)
+    out = []
+    for i, L in enumerate([18, 40, 25, 70, 33, 52]):
+        w = sy.Workload(f"job{i}", L=L, n_chains=int(rng.integers(3, 12)), total_sweeps=int(rng.choice([20, 30, 45])),
+                        window_d=8, global_every=5, sigma_deg=15.0, T0=1.0, T1=0.05,
+                        seed=0x5E0000 + i, protein_seed=50 + i, noise_seed=70 + i)
+        s_ref, y = gu.protein(w)
+        V_ref = float(__import__("oracle").energy(__import__("oracle").make_cfg(w),
+                                                   y.astype(np.float32).astype(np.float64), s_ref))
+        # one job gets a target it reaches quickly (an energy above the start), others 1.05 V_ref
+        target = 1e9 if i == 2 else 1.05 * V_ref
+        out.append((w, amh.make_config(w), y.astype(np.float32), target))
+    return out
+
+
+def _serve(jobs, **opts):
+    from paper_2211_03193_amd import amh
+    srv = amh.Server(**opts)
+    ids = [srv.submit(cfg, y, tg) for _, cfg, y, tg in jobs]
+    rounds = 0
+    while True:
+        a, p = srv.step()
+        rounds += 1
+        if a == 0 and p == 0:
+            break
+        assert rounds < 1000
+    status = [srv.job(j) for j in ids]
+    for j, s in zip(ids, status):
+        assert s["state"] == 2, (j, s, opts)
+    res = [srv.job(j, want_state=True) for j in ids]
+    srv.close()
+    return res
+
+
+def test_same_result_alone_and_in_the_mix():
+    gu.say("serve mix vs alone")
+    jobs = _jobs()
+    mix = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=4, sweeps_per_round=5)
+    alone = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=1, sweeps_per_round=5)
+    for (w, *_), a, b in zip(jobs, mix, alone):
+        assert a["state"] == b["state"] == 2
+        assert a["sweeps"] == b["sweeps"] and a["sweeps_to_target"] == b["sweeps_to_target"]
+        assert np.array_equal(a["s_best"], b["s_best"])
+        assert np.array_equal(a["v"], b["v"])
+        assert a["best_V"] == b["best_V"] == a["v"][:, 1].min()
+        assert a["t_submit"] <= a["t_admit"] <= a["t_done"]
+    # the easy target ends its job at the first anchor; the others run to their last sweep
+    assert mix[2]["reached"] == 1 and mix[2]["sweeps_to_target"] == 5 and mix[2]["sweeps"] == 5
+    for k in (0, 1, 3, 4, 5):
+        if not mix[k]["reached"]:
+            assert mix[k]["sweeps"] == jobs[k][0].total_sweeps
+
+
+def test_served_job_matches_a_plain_context():
+    gu.say("served vs plain context")
+    jobs = _jobs()[:2]
+    res = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=2, sweeps_per_round=7)
+    for (w, cfg, y, tg), r in zip(jobs, res):
+        ctx = gu.context(w, y.astype(np.float64))
+        ctx.set_target(tg)
+        ctx.sweep(r["sweeps"])
+        st = ctx.get_state()
+        assert np.array_equal(st["s_best"].cpu().numpy(), r["s_best"])
+        assert np.array_equal(st["v"].cpu().numpy(), r["v"])
+        ctx.close()
+
+
+def test_admission_respects_the_memory_budget():
+    gu.say("serve budget")
+    from paper_2211_03193_amd import amh
+    jobs = _jobs()
+    srv = amh.Server(hbm_budget_bytes=1, max_active=8, sweeps_per_round=5)
+    sizes = []
+    for _, cfg, y, tg in jobs:           # every job is larger than a 1-byte budget
+        with pytest.raises(amh.AmhError) as e:
+            srv.submit(cfg, y, tg)
+        assert e.value.status == amh.E_BUSY
+    srv.close()
+    probe = amh.Server(hbm_budget_bytes=1 << 40)
+    for _, cfg, y, tg in jobs:
+        sizes.append(probe.job(probe.submit(cfg, y, tg))["bytes"])
+    probe.close()
+    budget = sorted(sizes)[-1] + sorted(sizes)[-2]     # room for the two largest at most
+    srv = amh.Server(hbm_budget_bytes=budget, max_active=8, sweeps_per_round=5)
+    ids = [srv.submit(cfg, y, tg) for _, cfg, y, tg in jobs]
+    held_back = False
+    while True:
+        a, p = srv.step()
+        st = [srv.job(j) for j in ids]
+        active = [s for s in st if s["state"] == 1]
+        assert sum(s["bytes"] for s in active) <= budget
+        held_back |= p > 0 and a < 8
+        if a == 0 and p == 0:
+            break
+    assert all(s["state"] == 2 for s in st)
+    assert held_back
+    srv.close()

@@ -136,3 +136,28 @@ def test_protein_status_and_trace_length():
     s, V, it, st, tr = oracle.lbfgs_protein(cfg, y, s0, oracle.lbfgs_opts(n_iter=7))
     assert st == 1 and it == 7 and len(tr) == 8
     assert V == pytest.approx(tr[-1]) and V < tr[0]
+
+
+def test_replay_accepts_its_own_iterates_and_catches_a_planted_step():
+    w = sy.CFG1.replace(L=20)
+    s_ref = sy.reference_torsions(w.L, 6)
+    y = sy.distogram(sy.pair_distances(oracle.cb(s_ref)), 0.1, 7)
+    cfg = oracle.make_cfg(w)
+    opts = oracle.lbfgs_opts(n_iter=30)
+    s, V, it, st, tr, X = oracle.lbfgs_protein(cfg, y, sy.random_torsions(2 * w.L, 8), opts,
+                                               iterates=True)
+    assert X.shape == (it + 1, 2 * w.L) and it == 30
+    assert tr[-1] == pytest.approx(oracle.energy(cfg, y, X[-1]), rel=1e-14)
+    rc, rep = oracle.lbfgs_replay(cfg, y, X, opts)
+    assert rc == 0 and rep["n_steps"] == it and rep["n_fail"] == 0 and rep["n_forks"] == 0
+    assert rep["max_step_err"] < 1e-10         # only the rounding of x + a d remains
+    # a wrong step (a small error in one coordinate of one iterate) is caught there
+    Xb = X.copy()
+    Xb[12, 5] += 1e-4 * np.abs(X[12] - X[11]).max()
+    rc, rep = oracle.lbfgs_replay(cfg, y, Xb, opts)
+    assert rc == 1 and rep["first_fail"] == 11
+    # so is a step taken at another trial length without a near-tie
+    Xc = X.copy()
+    Xc[8:] += -0.5 * (X[8] - X[7])
+    rc, rep = oracle.lbfgs_replay(cfg, y, Xc, opts)
+    assert rc == 1 and rep["first_fail"] == 7
