@@ -166,6 +166,65 @@ def batch_leg(steps, warmup, n_proteins, tune_sweeps):
     }
 
 
+def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
+    """Poisson arrivals of folding jobs (L uniform on [50, 800], 64-512 chains, their
+    own Philox keys, target 1.05 V(s_ref)), served by continuous batching and by a
+    one-job-at-a-time queue; every job's best states must agree between the two."""
+    import torch
+    from paper_2211_03193_amd import amh, serving
+
+    dev = torch.device("cuda:0")
+    seed = 0x414D4805
+    Ls = sy.batch_lengths(n_jobs, 50, 800, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    chains = rng.choice([64, 128, 256, 512], size=n_jobs)
+    arrivals = sy.poisson_arrivals(rate, n_jobs, seed + 2)
+    jobs = []
+    for i, (L, C) in enumerate(zip(Ls, chains)):
+        w = sy.Workload(f"job{i:02d}-L{int(L)}", L=int(L), n_chains=int(C), total_sweeps=sweeps,
+                        window_d=12, seed=(seed << 16) + i, protein_seed=3000 + i, noise_seed=4000 + i)
+        s_ref = sy.reference_torsions(w.L, w.protein_seed)
+        atoms = amh.conformation(torch.from_numpy(s_ref[None]).to(dev))[0].cpu().numpy()
+        y = np.ascontiguousarray(sy.distogram(sy.pair_distances(atoms[:, 3, :]), w.eps, w.noise_seed),
+                                 dtype=np.float32)
+        probe = amh.Context(amh.make_config(w.replace(n_chains=1)), torch.from_numpy(y).to(dev))
+        v_ref = probe.energy(torch.from_numpy(s_ref[None]).to(dev))[0].item()
+        probe.close()
+        jobs.append((amh.make_config(w), y, 1.05 * v_ref))
+    torch.cuda.synchronize()
+    out = {}
+    results = {}
+    for name, max_active in (("continuous", 1 << 30), ("fifo", 1)):
+        srv = amh.Server(int(budget_gib * 2**30), max_active=max_active,
+                         sweeps_per_round=sweeps_per_round, plan=plan)
+        st = serving.run_trace(srv, jobs, arrivals)
+        out[name] = serving.summarise(st)
+        done = [s for s in st if s["state"] == 2]
+        out[name]["jobs_per_s"] = len(done) / out[name]["makespan_s"] if done else 0.0
+        props = sum(s["sweeps"] * jobs[i][0].n_chains * 2 * jobs[i][0].L for i, s in enumerate(st))
+        out[name]["proposals_per_s"] = props / out[name]["makespan_s"] if done else 0.0
+        results[name] = [srv.job(s["id"], want_state=True) if s["state"] == 2 else None for s in st]
+        srv.close()
+    same = all(a is not None and b is not None and np.array_equal(a["s_best"], b["s_best"])
+               and np.array_equal(a["v"], b["v"])
+               for a, b in zip(results["continuous"], results["fifo"]))
+    c, f = out["continuous"], out["fifo"]
+    return {
+        "metric": "p99 request latency", "value": c["p99_time_to_done_s"], "unit": "s",
+        "n_gpus": 1, "steps": n_jobs, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serve-{n_jobs}jobs-poisson{rate:g}-L50-800-64to512chains",
+                   "sweeps_per_job": sweeps, "sweeps_per_round": sweeps_per_round, "plan": plan,
+                   "hbm_budget_gib": budget_gib, "target": "1.05 V(s_ref)",
+                   "latency": "submit to completion (target reached or last sweep)"},
+        "continuous": c, "fifo": f,
+        "p99_speedup_vs_fifo": (f["p99_time_to_done_s"] / c["p99_time_to_done_s"]
+                                if c["p99_time_to_done_s"] else None),
+        "same_results_alone_and_in_mix": bool(same),
+    }
+
+
 def cpu_leg(w, cores, sweeps):
     import oracle
     s_ref = sy.reference_torsions(w.L, w.protein_seed)
@@ -194,9 +253,14 @@ def main():
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=80)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
                     help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
-                         "of lengths 50-600, 256 chains each, batched vs plain launches")
+                         "of lengths 50-600, 256 chains each, batched vs plain launches; serve: "
+                         "Poisson arrivals of jobs, continuous batching vs one job at a time")
+    ap.add_argument("--jobs", type=int, default=40, help="jobs in the serve workload")
+    ap.add_argument("--rate", type=float, default=20.0, help="mean arrivals per second (serve)")
+    ap.add_argument("--job-sweeps", type=int, default=100, help="sweeps per job at most (serve)")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="device-memory budget (serve)")
     ap.add_argument("--proteins", type=int, default=64, help="proteins in the batch workload")
     ap.add_argument("--tune-sweeps", type=int, default=10, help="sweeps per autotuner trial")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -217,8 +281,11 @@ def main():
               "GPUs with no per-step communication, see the design notes.", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    if args.workload == "batch":
-        out = batch_leg(args.steps, args.warmup, args.proteins, args.tune_sweeps)
+    if args.workload in ("batch", "serve"):
+        if args.workload == "batch":
+            out = batch_leg(args.steps, args.warmup, args.proteins, args.tune_sweeps)
+        else:
+            out = serve_leg(args.jobs, args.rate, args.job_sweeps, args.budget_gib, 10, 3)
         if rank == 0:
             print(json.dumps(out), flush=True)
         return

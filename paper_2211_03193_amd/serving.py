@@ -15,26 +15,29 @@ from . import amh
 
 def run_trace(server: amh.Server, jobs, arrivals, max_wall: float = 600.0) -> list[dict]:
     """jobs: list of (amh_config, y float32 host array, target); arrivals: seconds from
-    the start, non-decreasing.  Returns the final status of every job, in order."""
+    the start, non-decreasing.  Returns the final status of every job (with its
+    handle under "id"), in arrival order."""
     t0 = time.monotonic()
     ids = []
     i, n = 0, len(jobs)
     active = pending = 0
     while True:
         now = time.monotonic() - t0
+        if now > max_wall:
+            raise TimeoutError(f"trace not drained after {max_wall} s")
+        submitted = False
         while i < n and arrivals[i] <= now:
             cfg, y, target = jobs[i]
             ids.append(server.submit(cfg, y, target))
             i += 1
-        if i == n and active == 0 and pending == 0:
-            break
-        if now > max_wall:
-            raise TimeoutError(f"trace not drained after {max_wall} s")
-        if active == 0 and pending == 0:
-            time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
+            submitted = True
+        if submitted or active or pending:
+            active, pending = server.step()
             continue
-        active, pending = server.step()
-    return [server.job(j) for j in ids]
+        if i == n:
+            break
+        time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
+    return [dict(server.job(j), id=j) for j in ids]
 
 
 def summarise(status: list[dict]) -> dict:
