@@ -24,6 +24,24 @@ import numpy as np  # noqa: E402
 import synthetic as sy  # noqa: E402
 
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9    # FLOP/s: 256 CUs x 64 lanes x FMA x 2.4 GHz
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_L300_1024chains_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed counter record
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None once the kernel sources no
+    longer hash to the ones the counters were taken on."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for s in rec["sources"]:
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def host_cores() -> int:
@@ -251,7 +269,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--chains-per-group", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=80)
+    ap.add_argument("--cpu-sweeps", type=int, default=800,
+                    help="sweeps of the oracle CPU-baseline sample (2 chains per core)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
                     help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
@@ -321,7 +340,8 @@ def main():
                    "coord_dtype": "f64", "launch": r["info"]},
         "pair_evals_per_s": pairs_step * args.steps / r["wall"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch (HBM)",
                      "kernel": "sweep_kernel<4>", "avg_launch_ms": launch_s * 1e3,
                      "flops_per_pair": flops_pair, "pairs_per_launch": pairs_step},
         "energy": {"V_ref": r["V_ref"], "target": r["target"],
