@@ -21,7 +21,8 @@ class Cfg(C.Structure):
         ("L", C.c_int32), ("n_bins", C.c_int32), ("d_min", C.c_double), ("bin_w", C.c_double),
         ("window_d", C.c_int32), ("global_every", C.c_int32), ("anchor_every", C.c_int32),
         ("pad0", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
-        ("total_sweeps", C.c_int64), ("seed", C.c_uint64),
+        ("total_sweeps", C.c_int64), ("seed", C.c_uint64), ("sigma_end", C.c_double),
+        ("n_cascade", C.c_int32), ("cascade_d", C.c_int32 * 3),
     ]
 
 
@@ -98,6 +99,11 @@ def lib():
     L.oracle_beta.restype = C.c_double
     L.oracle_is_global.argtypes = [P(Cfg), C.c_int64]
     L.oracle_is_global.restype = C.c_int32
+    L.oracle_sigma.argtypes = [P(Cfg), C.c_int64]
+    L.oracle_sigma.restype = C.c_double
+    L.oracle_window_d.argtypes = [P(Cfg), C.c_int64]
+    L.oracle_window_d.restype = C.c_int32
+    L.oracle_perturb.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, C.c_int32, _D]
     L.oracle_nerf.argtypes = [C.c_int32, _D, _D]
     L.oracle_geometry_constants.argtypes = [_D]
     L.oracle_pair_energy.argtypes = [_D, C.c_int32, C.c_double, C.c_double, C.c_double]
@@ -139,9 +145,12 @@ def lib():
 
 def make_cfg(w) -> Cfg:
     """Oracle config from a synthetic.Workload."""
+    casc = list(getattr(w, "cascade", ()))
     return Cfg(L=w.L, n_bins=w.n_bins, d_min=w.d_min, bin_w=w.bin_w, window_d=w.window_d,
                global_every=w.global_every, anchor_every=w.anchor_period, pad0=0,
-               sigma=w.sigma, T0=w.T0, T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed)
+               sigma=w.sigma, T0=w.T0, T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed,
+               sigma_end=math.radians(getattr(w, "sigma_end_deg", 0.0)), n_cascade=len(casc),
+               cascade_d=(C.c_int32 * 3)(*(casc + [0] * (3 - len(casc)))))
 
 
 def _f64(a):
@@ -155,6 +164,21 @@ def philox(ctr, key) -> np.ndarray:
     out = np.empty_like(ctr)
     lib().oracle_philox_batch(ctr.shape[0], ctr, key, out)
     return out
+
+
+def sigma_at(cfg: Cfg, t: int) -> float:
+    return lib().oracle_sigma(C.byref(cfg), t)
+
+
+def window_at(cfg: Cfg, t: int) -> int:
+    return lib().oracle_window_d(C.byref(cfg), t)
+
+
+def perturb(seed: int, chain: int, tag: int, amplitude: float, s) -> np.ndarray:
+    """Noisy restart of one chain's torsions (a copy is returned)."""
+    s = _f64(s).copy()
+    lib().oracle_perturb(seed, chain, tag, amplitude, s.size, s)
+    return s
 
 
 def proposal(seed: int, chain: int, t: int, k: int, sigma: float) -> tuple[float, float]:

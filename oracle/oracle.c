@@ -93,6 +93,38 @@ int32_t oracle_is_global(const oracle_cfg *cfg, int64_t t) {
   return cfg->global_every > 0 && ((t + 1) % cfg->global_every) == 0;
 }
 
+/* Proposal width of sweep t: constant, or reduced geometrically from sigma to
+ * sigma_end over the schedule (Sec. 2.3: 10 to 4 degrees over a run). */
+double oracle_sigma(const oracle_cfg *cfg, int64_t t) {
+  if (cfg->sigma_end > 0.0 && cfg->sigma > 0.0 && cfg->total_sweeps > 1)
+    return cfg->sigma * pow(cfg->sigma_end / cfg->sigma, (double)t / (double)(cfg->total_sweeps - 1));
+  return cfg->sigma;
+}
+
+/* Localization radius of (localized) sweep t: window_d, then the cascade radii in
+ * turn (Sec. 2.2: several localization ranges may be cascaded). */
+int32_t oracle_window_d(const oracle_cfg *cfg, int64_t t) {
+  int32_t r = (int32_t)(t % (1 + cfg->n_cascade));
+  return r == 0 ? cfg->window_d : cfg->cascade_d[r - 1];
+}
+
+/* Noisy restart (the second scheme of Sec. 3): every torsion moves by a uniform
+ * amount in [-amplitude, amplitude], drawn from Philox at counter (k, tag, chain, 1),
+ * and is wrapped into (-pi, pi]. */
+void oracle_perturb(uint64_t seed, uint32_t chain, uint32_t tag, double amplitude, int32_t n,
+                    double *s) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int32_t k = 0; k < n; ++k) {
+    uint32_t ctr[4] = {(uint32_t)k, tag, chain, 1u}, out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    double u = unit_open(out[0]);
+    double a = s[k] + amplitude * (2.0 * u - 1.0);
+    if (a > PI_D) a -= TWO_PI_D;
+    else if (a <= -PI_D) a += TWO_PI_D;
+    s[k] = a;
+  }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Geometry G(s) by NeRF (Parsons et al., J. Comput. Chem. 26, 2005):
  * D is placed from A, B, C with |CD| = l, angle BCD = theta, dihedral ABCD = chi:
@@ -356,7 +388,11 @@ void oracle_grad(const oracle_cfg *cfg, const double *y, const double *s, double
 static int cfg_ok(const oracle_cfg *cfg) {
   return cfg && cfg->L >= 2 && cfg->n_bins >= 4 && cfg->bin_w > 0.0 && cfg->window_d >= 0 &&
          cfg->global_every >= 0 && cfg->anchor_every >= 1 && cfg->T0 > 0.0 && cfg->T1 > 0.0 &&
-         cfg->total_sweeps >= 1 && cfg->sigma >= 0.0;
+         cfg->total_sweeps >= 1 && cfg->sigma >= 0.0 && cfg->sigma_end >= 0.0 &&
+         cfg->n_cascade >= 0 && cfg->n_cascade <= 3 &&
+         (cfg->n_cascade < 1 || cfg->cascade_d[0] >= 0) &&
+         (cfg->n_cascade < 2 || cfg->cascade_d[1] >= 0) &&
+         (cfg->n_cascade < 3 || cfg->cascade_d[2] >= 0);
 }
 
 void oracle_chain_init(const oracle_cfg *cfg, const double *y, int32_t n_chains,
@@ -443,20 +479,22 @@ static void run_chain(const oracle_cfg *cfg, const double *y, uint32_t chain, in
   int64_t step = 0, ai = 0;
   for (int64_t t = t_begin; t < t_begin + n_sweeps; ++t) {
     int32_t global = oracle_is_global(cfg, t);
-    double beta = oracle_beta(cfg, t);
+    double beta = oracle_beta(cfg, t), sigma = oracle_sigma(cfg, t);
+    oracle_cfg ct = *cfg;               /* this sweep's localization radius */
+    ct.window_d = oracle_window_d(cfg, t);
     for (int32_t k = 0; k < n; ++k, ++step) {
       double delta, log_u2, S;
       int32_t last;
-      oracle_proposal(cfg->seed, chain, t, k, cfg->sigma, &delta, &log_u2);
+      oracle_proposal(cfg->seed, chain, t, k, sigma, &delta, &log_u2);
       double dE;
       if (mode == 0) {
         /* brute force: both energies from full rebuilds of s and s' */
-        dE = oracle_delta_e(cfg, y, s, k, delta, global, 0, &S);
+        dE = oracle_delta_e(&ct, y, s, k, delta, global, 0, &S);
         memcpy(w.sp, s, sizeof(double) * n);
         w.sp[k] = wrap_angle(s[k] + delta);
         last = L - 1;
       } else {
-        dE = ws_eval(cfg, y, &w, k, delta, global, &S, &last);
+        dE = ws_eval(&ct, y, &w, k, delta, global, &S, &last);
       }
       int acc = (dE <= 0.0) || (log_u2 < -beta * dE);
       if (step_log) { step_log[2 * step] = dE; step_log[2 * step + 1] = delta; }
@@ -526,12 +564,14 @@ int32_t oracle_replay(const oracle_cfg *cfg, const double *y, uint32_t chain_id,
   int64_t step = 0, ai = 0;
   for (int64_t t = t_begin; t < t_begin + n_sweeps; ++t) {
     int32_t global = oracle_is_global(cfg, t);
-    double beta = oracle_beta(cfg, t);
+    double beta = oracle_beta(cfg, t), sigma = oracle_sigma(cfg, t);
+    oracle_cfg ct = *cfg;
+    ct.window_d = oracle_window_d(cfg, t);
     for (int32_t k = 0; k < n; ++k, ++step) {
       double delta, log_u2, S;
       int32_t last;
-      oracle_proposal(cfg->seed, chain_id, t, k, cfg->sigma, &delta, &log_u2);
-      double dE = ws_eval(cfg, y, &w, k, delta, global, &S, &last);
+      oracle_proposal(cfg->seed, chain_id, t, k, sigma, &delta, &log_u2);
+      double dE = ws_eval(&ct, y, &w, k, delta, global, &S, &last);
       int acc_or = (dE <= 0.0) || (log_u2 < -beta * dE);
       int acc_g = gpu_acc[step] ? 1 : 0;
       double dg = gpu_dE[step];

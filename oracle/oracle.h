@@ -34,6 +34,9 @@ typedef struct {
   double T0, T1;        /* geometric temperature schedule over total_sweeps */
   int64_t total_sweeps; /* S */
   uint64_t seed;        /* Philox key */
+  double sigma_end;     /* > 0: proposal width decays geometrically to sigma_end over S */
+  int32_t n_cascade;    /* extra localization radii taken in turn with window_d, 0..3 */
+  int32_t cascade_d[3]; /* sweep t uses radius r = t % (1 + n_cascade): 0 window_d, else cascade_d[r-1] */
 } oracle_cfg;
 
 typedef struct {
@@ -62,6 +65,11 @@ void oracle_proposal(uint64_t seed, uint32_t chain, int64_t t, int32_t k, double
 
 double oracle_beta(const oracle_cfg *cfg, int64_t t);
 int32_t oracle_is_global(const oracle_cfg *cfg, int64_t t);
+double oracle_sigma(const oracle_cfg *cfg, int64_t t);
+int32_t oracle_window_d(const oracle_cfg *cfg, int64_t t);
+/* Noisy restart: s_k += amplitude (2u - 1), u from Philox at (k, tag, chain, 1), wrapped. */
+void oracle_perturb(uint64_t seed, uint32_t chain, uint32_t tag, double amplitude, int32_t n,
+                    double *s);
 
 /* Geometry G(s): NeRF chain of ideal backbone + virtual C-beta. */
 void oracle_nerf(int32_t L, const double *s, double *atoms);

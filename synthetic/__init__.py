@@ -144,6 +144,8 @@ class Workload:
     bin_w: float = BIN_W
     anchor_every: int = 0         # 0 -> same as global_every (or 10 when local-only)
     trace_chains: list = field(default_factory=list)
+    sigma_end_deg: float = 0.0    # > 0: proposal width decays geometrically to this
+    cascade: tuple = ()           # extra localization radii taken in turn with window_d
 
     @property
     def sigma(self) -> float:
