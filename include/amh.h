@@ -60,6 +60,12 @@ typedef struct {
   int32_t chains_per_group; /* chains that share one workgroup, 0 = choose (1, 2 or 4) */
   int32_t waves_per_group;  /* wavefronts per workgroup (<= 8), 0 = choose; >= chains_per_group */
   int32_t reserved;
+  double sigma_end;       /* > 0: the proposal width decays geometrically from sigma to
+                             sigma_end over the schedule (Sec. 2.3: 10 to 4 degrees);
+                             0 = constant sigma */
+  int32_t n_cascade;      /* extra localization radii, 0..3 (Sec. 2.2: cascaded ranges): */
+  int32_t cascade_d[3];   /* localized sweep t uses window_d if t % (1 + n_cascade) == 0,
+                             else cascade_d[t % (1 + n_cascade) - 1] (each >= 0) */
 } amh_config;
 
 /* Create a sampler.
@@ -106,6 +112,14 @@ amh_status amh_get_state(amh_ctx* ctx, double* s_dev, double* s_best_dev, double
 amh_status amh_set_state(amh_ctx* ctx, const double* s_dev, const double* s_best_dev,
                          const double* v_dev, const int64_t* counters_dev,
                          const double* atoms_dev, int64_t t);
+
+/* Noisy restart (the second scheme of Sec. 3 adds a uniform draw in [-10, 10] degrees
+ * to every torsion): every torsion of every chain moves by amplitude (2u - 1), u from
+ * Philox at counter (k, tag, chain_offset + c, 1) with the context's key, and is
+ * wrapped into (-pi, pi]; the coordinates are rebuilt, the current V re-anchored in
+ * float64, and the best state replaced where V is lower.  Counters and the sweep
+ * index are kept.  amplitude >= 0 (rad); use a new tag for every restart. */
+amh_status amh_perturb(amh_ctx* ctx, double amplitude, uint32_t tag);
 
 /* Time-to-target: the first anchor with V <= target records its sweep count in
  * counters[c][2] (default target: -infinity, never reached). */

@@ -34,6 +34,7 @@ class AmhConfig(C.Structure):
         ("anchor_every", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
         ("total_sweeps", C.c_int64), ("seed", C.c_uint64), ("chain_offset", C.c_uint32),
         ("chains_per_group", C.c_int32), ("waves_per_group", C.c_int32), ("reserved", C.c_int32),
+        ("sigma_end", C.c_double), ("n_cascade", C.c_int32), ("cascade_d", C.c_int32 * 3),
     ]
 
 
@@ -92,6 +93,7 @@ def lib():
         "amh_get_state": [_P, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)],
         "amh_set_state": [_P, _P, _P, _P, _P, _P, C.c_int64],
         "amh_set_target": [_P, C.c_double],
+        "amh_perturb": [_P, C.c_double, C.c_uint32],
         "amh_set_trace": [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, C.c_int64, _P, C.c_int64],
         "amh_poll": [_P],
         "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -143,7 +145,12 @@ def make_config(w, **over) -> AmhConfig:
                     d_min=w.d_min, bin_w=w.bin_w, global_every=w.global_every,
                     anchor_every=w.anchor_period, sigma=math.radians(w.sigma_deg), T0=w.T0,
                     T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed, chain_offset=0,
-                    chains_per_group=0, waves_per_group=0, reserved=0)
+                    chains_per_group=0, waves_per_group=0, reserved=0,
+                    sigma_end=math.radians(getattr(w, "sigma_end_deg", 0.0)))
+    casc = list(getattr(w, "cascade", ()))
+    cfg.n_cascade = len(casc)
+    for i, d in enumerate(casc):
+        cfg.cascade_d[i] = d
     for k, v in over.items():
         setattr(cfg, k, v)
     return cfg
@@ -255,6 +262,10 @@ class Context:
 
     def set_target(self, target: float) -> None:
         check(lib().amh_set_target(self._h, target))
+
+    def perturb(self, amplitude: float, tag: int) -> None:
+        """Noisy restart of every chain (amh_perturb): uniform in [-amplitude, amplitude] rad."""
+        check(lib().amh_perturb(self._h, amplitude, tag))
 
     def set_trace(self, chain_ids, n_sweeps: int) -> dict:
         """Trace every proposal of the given chains (<= 4) over the next n_sweeps sweeps."""

@@ -15,7 +15,7 @@
 #include "amh_grad.h"
 #include "amh_kernels.h"
 
-static_assert(sizeof(amh_config) == 96, "amh_config layout");
+static_assert(sizeof(amh_config) == 120, "amh_config layout");
 static_assert(sizeof(amh_lbfgs_opts) == 48, "amh_lbfgs_opts layout");
 
 namespace {
@@ -95,6 +95,11 @@ amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
   if (c->global_every < 0) return sfail(AMH_E_INVAL, "global_every=%d < 0", c->global_every);
   if (c->anchor_every < 1) return sfail(AMH_E_INVAL, "anchor_every=%d < 1", c->anchor_every);
   if (!(c->sigma >= 0.0) || !std::isfinite(c->sigma)) return sfail(AMH_E_INVAL, "sigma must be finite and >= 0");
+  if (!(c->sigma_end >= 0.0) || !std::isfinite(c->sigma_end))
+    return sfail(AMH_E_INVAL, "sigma_end must be finite and >= 0");
+  if (c->n_cascade < 0 || c->n_cascade > 3) return sfail(AMH_E_INVAL, "n_cascade=%d outside [0, 3]", c->n_cascade);
+  for (int i = 0; i < c->n_cascade; ++i)
+    if (c->cascade_d[i] < 0) return sfail(AMH_E_INVAL, "cascade_d[%d]=%d < 0", i, c->cascade_d[i]);
   if (!(c->T0 > 0.0) || !(c->T1 > 0.0) || !std::isfinite(c->T0) || !std::isfinite(c->T1))
     return sfail(AMH_E_INVAL, "T0 and T1 must be finite and > 0");
   if (c->total_sweeps < 1 || c->total_sweeps > 0xFFFFFFFFLL)
@@ -181,6 +186,9 @@ amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   P.L = c.L;
   P.C = c.n_chains;
   P.half_window = c.window_d / 2;
+  P.n_cascade = c.n_cascade;
+  for (int i = 0; i < 3; ++i) P.cascade_hw[i] = i < c.n_cascade ? c.cascade_d[i] / 2 : 0;
+  P.sigma_end = c.sigma_end;
   P.global_every = c.global_every;
   P.anchor_every = c.anchor_every;
   P.sigma = c.sigma;
@@ -387,6 +395,25 @@ amh_status amh_set_state(amh_ctx* x, const double* s_dev, const double* s_best_d
   }
   x->t = t;
   return AMH_OK;
+}
+
+amh_status amh_perturb(amh_ctx* x, double amplitude, uint32_t tag) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (!(amplitude >= 0.0) || !std::isfinite(amplitude)) return sfail(AMH_E_INVAL, "amplitude must be finite and >= 0");
+  const amh_config& c = x->cfg;
+  const int64_t total = (int64_t)c.n_chains * 2 * c.L;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(amh::perturb_kernel, dim3(blocks), dim3(256), 0, x->stream, x->s, total, 2 * c.L,
+                     c.chain_offset, tag, (uint32_t)c.seed, (uint32_t)(c.seed >> 32), amplitude);
+  HIP_OK(hipGetLastError());
+  amh::ConfParams P = conf_base(x);   // rebuild coordinates, re-anchor V, keep the best
+  P.s_in = x->s;
+  P.atoms64_out = x->atoms;
+  P.v_state = x->v;
+  P.s_best = x->s_best;
+  P.keep_best = 1;
+  return launch_conf(P, c.n_chains, x->stream);
 }
 
 amh_status amh_set_target(amh_ctx* x, double target) {

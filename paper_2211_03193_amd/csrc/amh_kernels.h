@@ -22,7 +22,8 @@ struct SweepParams {
   double d_min, bin_w;
   // run
   int L, C, half_window, global_every, anchor_every;
-  double sigma, T0, T1;
+  int n_cascade, cascade_hw[3];   // extra window half-widths taken in turn with half_window
+  double sigma, sigma_end, T0, T1;  // sigma_end > 0: geometric decay of the proposal width
   int64_t S, t0, n_sweeps;
   uint32_t key0, key1, chain_offset;
   double target;
@@ -60,6 +61,7 @@ struct ConfParams {
   double* v_state;      // [B][2]
   int64_t* counters;    // [B][4]
   double* s_best;       // [B][2L]
+  int keep_best;        // v_state: set V as current, lower the best (and s_best) only if V is lower
   unsigned int* err;
 };
 
@@ -72,6 +74,8 @@ __global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, flo
                               float* dev, unsigned int* err);
 __global__ void conf_energy_kernel(ConfParams P);
 __global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
+__global__ void perturb_kernel(double* s, int64_t n_total, int n, uint32_t chain_offset, uint32_t tag,
+                               uint32_t k0, uint32_t k1, double amplitude);
 template <int G>
 __global__ void sweep_kernel(SweepParams P);
 template <int G>

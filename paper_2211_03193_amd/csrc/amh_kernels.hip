@@ -65,6 +65,19 @@ __global__ void ingest_kernel(const float* __restrict__ y, int64_t P, int nb, in
   if (bad) atomicOr(err, kErrTable);
 }
 
+// Noisy restart: s_k += amplitude (2u - 1) with u from Philox at (k, tag, chain, 1),
+// wrapped into (-pi, pi]; one thread per torsion of every chain.
+__global__ void perturb_kernel(double* __restrict__ s, int64_t n_total, int n, uint32_t chain_offset,
+                               uint32_t tag, uint32_t k0, uint32_t k1, double amplitude) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / n), k = (int)(e - (int64_t)c * n);
+    const U4 r = philox10(U4{(uint32_t)k, tag, chain_offset + (uint32_t)c, 1u}, k0, k1);
+    const double u = ((double)r.x + 0.5) * (1.0 / 4294967296.0);
+    s[e] = wrap_angle(s[e] + amplitude * (2.0 * u - 1.0));
+  }
+}
+
 __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint32_t k0, uint32_t k1,
                               uint32_t* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -139,17 +152,24 @@ __global__ void conf_energy_kernel(ConfParams P) {
     for (int m = tid; m < 2 * L; m += blockDim.x) P.s_out[(size_t)b * 2 * L + m] = s[m];
   if (P.table) {
     energy64(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, x64, red64, Vs);
+    const double V = Vs[0];
+    // keep_best: V becomes the current energy and replaces the best one only if lower
+    // (every thread decides from the old best before it is overwritten)
+    const bool better = !(P.v_state && P.keep_best) || V < P.v_state[2 * b + 1];
+    __syncthreads();
     if (tid == 0) {
-      const double V = Vs[0];
       if (!isfinite(V)) atomicOr(P.err, kErrEnergy);
       if (P.V_out) P.V_out[b] = V;
-      if (P.v_state) { P.v_state[2 * b] = V; P.v_state[2 * b + 1] = V; }
+      if (P.v_state) {
+        P.v_state[2 * b] = V;
+        if (better) P.v_state[2 * b + 1] = V;
+      }
       if (P.counters) {
         P.counters[4 * b + 0] = 0; P.counters[4 * b + 1] = 0;
         P.counters[4 * b + 2] = -1; P.counters[4 * b + 3] = 0;
       }
     }
-    if (P.s_best)
+    if (P.s_best && better)
       for (int m = tid; m < 2 * L; m += blockDim.x) P.s_best[(size_t)b * 2 * L + m] = s[m];
   }
 }
@@ -192,12 +212,28 @@ struct Batch {  // proposal randoms of 64 consecutive proposals, one per lane
   double delta, log_u, cd, sd;
 };
 
+// Proposal width of sweep t: constant, or reduced geometrically from sigma to
+// sigma_end over the schedule (Sec. 2.3 reduces it from 10 to 4 degrees).
+__device__ __forceinline__ double sigma_at(const SweepParams& P, int64_t t) {
+  if (P.sigma_end > 0.0 && P.sigma > 0.0 && P.S > 1)
+    return P.sigma * pow(P.sigma_end / P.sigma, (double)t / (double)(P.S - 1));
+  return P.sigma;
+}
+
+// Window half-width of localized sweep t: window_d, then the cascade radii in turn
+// (Sec. 2.2 allows several localization ranges).
+__device__ __forceinline__ int half_window_at(const SweepParams& P, int64_t t) {
+  if (P.n_cascade == 0) return P.half_window;
+  const int r = (int)((uint32_t)t % (uint32_t)(1 + P.n_cascade));   // t < 2^32
+  return r == 0 ? P.half_window : r == 1 ? P.cascade_hw[0] : r == 2 ? P.cascade_hw[1] : P.cascade_hw[2];
+}
+
 __device__ __forceinline__ Batch fill_batch(const SweepParams& P, int kb, uint32_t t,
                                             uint32_t chain, int lane) {
   const int k = kb + lane;
   Batch b{0.0, 0.0, 1.0, 0.0};
   if (k < 2 * P.L) {
-    const Draw d = proposal_draw((uint32_t)k, t, chain, P.key0, P.key1, P.sigma);
+    const Draw d = proposal_draw((uint32_t)k, t, chain, P.key0, P.key1, sigma_at(P, t));
     b.delta = d.delta; b.log_u = d.log_u; b.cd = d.cd; b.sd = d.sd;
   }
   return b;
@@ -247,9 +283,9 @@ __device__ __forceinline__ bool wait_progress(const SweepParams& P, const int* c
 }
 
 __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain, int64_t t,
-                            double beta, int lane, int slot, int64_t& n_acc, const Pipe& pipe,
-                            bool& stalled) {
-  const int L = P.L, n = 2 * L, h = P.half_window;
+                            double beta, int h, int h_prev, int lane, int slot, int64_t& n_acc,
+                            const Pipe& pipe, bool& stalled) {
+  const int L = P.L, n = 2 * L;
   double* __restrict__ x64 = S.x64(g);
   double* __restrict__ s = S.s(g);
   const Spline32 sp{P.inv_w, P.off, P.tmax};
@@ -264,7 +300,9 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
     const int c = k >> 1, p = (k & 1) ? c + 1 : c;
     const int lo = c - h > 0 ? c - h : 0, hi = c + h < L - 1 ? c + h : L - 1;
     if (pipe.wait_on) {
-      const int need = 2 * c + 4 * h + 2 < n ? 2 * c + 4 * h + 2 : n;
+      // the previous sweep (half-width h_prev) must be done with every proposal whose
+      // window reaches residue c + h, i.e. with all proposals up to c' = c + h + h_prev
+      const int need = 2 * (c + h + h_prev) + 2 < n ? 2 * (c + h + h_prev) + 2 : n;
       wait_progress(P, pipe.wait_on, (pipe.m - 1) * 4096 + need, stalled);
     }
     // residues entering the window take the transform accumulated so far
@@ -453,7 +491,9 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
           pipe.m = m;
           pipe.publish = S.prog(W) + lg * W + stage;
           pipe.wait_on = m > 0 ? S.prog(W) + lg * W + ((m - 1) % nstage) : nullptr;
-          local_sweep(P, S, lg, c0 + lg, tm, 1.0 / Tm, lane, lslot, acc_local_stage, pipe, stalled);
+          local_sweep(P, S, lg, c0 + lg, tm, 1.0 / Tm, half_window_at(P, tm),
+                      tm > 0 ? half_window_at(P, tm - 1) : 0, lane, lslot, acc_local_stage, pipe,
+                      stalled);
         }
       }
       __syncthreads();

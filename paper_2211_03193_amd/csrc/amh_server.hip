@@ -30,7 +30,7 @@
 #include "amh_error.h"
 
 static_assert(sizeof(amh_server_opts) == 24, "amh_server_opts layout");
-static_assert(sizeof(amh_job) == 112, "amh_job layout");
+static_assert(sizeof(amh_job) == 136, "amh_job layout");
 static_assert(sizeof(amh_job_status) == 72, "amh_job_status layout");
 
 namespace {

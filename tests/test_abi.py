@@ -30,9 +30,10 @@ def test_library_exports_every_declared_symbol(amh):
 
 
 def test_config_struct_layout(amh):
-    # the ctypes mirror must match the C layout: 96 bytes, seed at offset 72
-    assert C.sizeof(amh.AmhConfig) == 96
+    # the ctypes mirror must match the C layout (static_assert in the library): 120 bytes
+    assert C.sizeof(amh.AmhConfig) == 120
     assert amh.AmhConfig.seed.offset == 72 and amh.AmhConfig.chain_offset.offset == 80
+    assert amh.AmhConfig.sigma_end.offset == 96 and amh.AmhConfig.cascade_d.offset == 108
 
 
 def _good():
@@ -46,7 +47,8 @@ def _good():
     ("bin_w", 0.0), ("global_every", -2), ("anchor_every", 0), ("sigma", -0.1),
     ("sigma", float("nan")), ("T0", 0.0), ("T1", -1.0), ("total_sweeps", 0),
     ("total_sweeps", 2**32), ("chains_per_group", 3), ("waves_per_group", 9),
-    ("d_min", float("inf")),
+    ("d_min", float("inf")), ("sigma_end", -1.0), ("sigma_end", float("inf")), ("n_cascade", 4),
+    ("n_cascade", -1),
 ])
 def test_invalid_config_rejected_on_host(amh, field, value):
     cfg = _good()
@@ -108,7 +110,7 @@ def test_server_calls_reject_null_arguments(amh):
 
 def test_server_struct_layouts(amh):
     assert C.sizeof(amh.ServerOpts) == 24
-    assert C.sizeof(amh.Job) == 96 + 8 + 8 and amh.Job.target.offset == 104
+    assert C.sizeof(amh.Job) == 120 + 8 + 8 and amh.Job.target.offset == 128
     assert C.sizeof(amh.JobStatus) == 72 and amh.JobStatus.best_V.offset == 24
 
 
