@@ -243,6 +243,81 @@ def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
     }
 
 
+def variants_leg(samples, chains):
+    """The paper's schemes (Sec. 3, Fig. 3 columns 1-5, and the Sec. 2.3 restart
+    procedure) on one synthetic 100-residue protein, `samples` samples each (a
+    sweep for MH schemes, an iteration for L-BFGS), `chains` independent chains;
+    then the beta sweep of Fig. 5 and the chain-count study of Fig. 4C."""
+    import torch
+    from paper_2211_03193_amd import amh, hybrid, variants
+
+    dev = torch.device("cuda:0")
+    # Alt-MH as benchmarked in Sec. 3: cycles of 20 localized (d = 5) and 80 global
+    # sweeps, width 10 -> 4 degrees; every scheme anneals 0.1 < beta < 1
+    w = sy.Workload("variants-L100", L=100, n_chains=chains, total_sweeps=samples, window_d=5,
+                    global_every=100, n_global=80, sigma_deg=10.0, sigma_end_deg=4.0,
+                    T0=10.0, T1=1.0, seed=0x414D4806, protein_seed=6, noise_seed=106)
+    s_ref = sy.reference_torsions(w.L, w.protein_seed)
+    atoms = amh.conformation(torch.from_numpy(s_ref[None]).to(dev))[0].cpu().numpy()
+    y = torch.from_numpy(np.ascontiguousarray(
+        sy.distogram(sy.pair_distances(atoms[:, 3, :]), w.eps, w.noise_seed), dtype=np.float32)).to(dev)
+    probe = amh.Context(amh.make_config(w.replace(n_chains=1)), y)
+    V_ref = probe.energy(torch.from_numpy(s_ref[None]).to(dev))[0].item()
+    probe.close()
+    res, secs = {}, {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res[name] = fn()
+        torch.cuda.synchronize()
+        secs[name] = time.perf_counter() - t0
+
+    mh_w = w.replace(sigma_end_deg=0.0)
+    timed("1_mh_annealed", lambda: variants.mh_noisy_restarts(mh_w, y, every=samples + 1))
+    timed("2_mh_noisy_restarts", lambda: variants.mh_noisy_restarts(mh_w, y, every=100))
+
+    def alt():
+        ctx = amh.Context(amh.make_config(w), y)
+        ctx.sweep(samples)
+        v = ctx.energy(which=1)[0].min().item()
+        ctx.close()
+        return {"best": v}
+    timed("3_alt_mh", alt)
+    timed("4_lbfgs_noisy_restarts", lambda: variants.lbfgs_noisy_restarts(w, y, batches=samples // 100))
+
+    def col5():
+        # its localized-MH phases (20 sweeps per batch of 100 samples) anneal over their own run
+        ctx = amh.Context(amh.make_config(w.replace(global_every=0, n_global=1,
+                                                    total_sweeps=samples // 100 * 20)), y)
+        hybrid.lbfgs_with_localized_mh(ctx, cycles=samples // 100, lbfgs_iters=80, mh_sweeps=20,
+                                       final_lbfgs=False)
+        v = ctx.energy(which=1)[0].min().item()
+        ctx.close()
+        return {"best": v}
+    timed("5_lbfgs_localized_mh", col5)
+    timed("alt_mh_10_restarts", lambda: variants.alt_mh_restarts(w.replace(total_sweeps=samples // 10), y, runs=10))
+    props82k = 82000 // (2 * w.L)
+    timed("beta_sweep", lambda: variants.beta_sweep(w.replace(total_sweeps=props82k, sigma_end_deg=0.0), y,
+                                                     betas=[0.01, 0.1, 1.0, 10.0, 100.0], runs=25))
+    timed("chain_counts", lambda: variants.chain_count_study(w.replace(total_sweeps=props82k), y,
+                                                              counts=(10, 1000)))
+    best = {k: v["best"] for k, v in res.items() if "best" in v}
+    return {
+        "metric": "lowest energy", "value": best["3_alt_mh"], "unit": "nats", "n_gpus": 1,
+        "steps": samples, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "variants-L100", "chains": chains, "samples": samples,
+                   "window_d": 5, "cycle": [20, 80], "sigma_deg": [10.0, 4.0], "beta": [0.1, 1.0],
+                   "beta_sweep_proposals_per_run": props82k * 2 * w.L},
+        "V_ref": V_ref, "best": best, "seconds": secs,
+        "alt_mh_gain_vs_mh": (best["1_mh_annealed"] - best["3_alt_mh"]) / best["1_mh_annealed"],
+        "alt_mh_gain_vs_noisy_restarts": (best["2_mh_noisy_restarts"] - best["3_alt_mh"]) / best["2_mh_noisy_restarts"],
+        "restarts": res["alt_mh_10_restarts"]["runs"], "beta_sweep": res["beta_sweep"],
+        "chain_counts": res["chain_counts"]["counts"],
+    }
+
+
 def cpu_leg(w, cores, sweeps):
     import oracle
     s_ref = sy.reference_torsions(w.L, w.protein_seed)
@@ -272,7 +347,7 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=800,
                     help="sweeps of the oracle CPU-baseline sample (2 chains per core)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
-    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "variants"], default="single",
                     help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
                          "of lengths 50-600, 256 chains each, batched vs plain launches; serve: "
                          "Poisson arrivals of jobs, continuous batching vs one job at a time")
@@ -280,6 +355,8 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="mean arrivals per second (serve)")
     ap.add_argument("--job-sweeps", type=int, default=100, help="sweeps per job at most (serve)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="device-memory budget (serve)")
+    ap.add_argument("--samples", type=int, default=10000, help="samples per scheme (variants)")
+    ap.add_argument("--variant-chains", type=int, default=64, help="chains per scheme (variants)")
     ap.add_argument("--proteins", type=int, default=64, help="proteins in the batch workload")
     ap.add_argument("--tune-sweeps", type=int, default=10, help="sweeps per autotuner trial")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -300,11 +377,13 @@ def main():
               "GPUs with no per-step communication, see the design notes.", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    if args.workload in ("batch", "serve"):
+    if args.workload in ("batch", "serve", "variants"):
         if args.workload == "batch":
             out = batch_leg(args.steps, args.warmup, args.proteins, args.tune_sweeps)
-        else:
+        elif args.workload == "serve":
             out = serve_leg(args.jobs, args.rate, args.job_sweeps, args.budget_gib, 10, 3)
+        else:
+            out = variants_leg(args.samples, args.variant_chains)
         if rank == 0:
             print(json.dumps(out), flush=True)
         return

@@ -48,8 +48,9 @@ typedef struct {
                              residues in [k/2 - d/2, k/2 + d/2] (local energy, Sec. 2.3) */
   double d_min;           /* left edge of bin 0 (A); knot b sits at d_min + bin_w (b + 1/2) */
   double bin_w;           /* bin width (A) > 0 */
-  int32_t global_every;   /* sweep t is a global-MH sweep iff global_every > 0 and
-                             (t+1) % global_every == 0, otherwise localized (Algorithm 1) */
+  int32_t global_every;   /* cycle length: sweep t is a global-MH sweep iff global_every > 0
+                             and t % global_every >= global_every - n_global, otherwise
+                             localized (Algorithm 1's alternation, localized first) */
   int32_t anchor_every;   /* anchors (FP64 energy, best state) after sweep t iff
                              (t+1) % anchor_every == 0; >= 1 */
   double sigma;           /* proposal standard deviation (rad) >= 0 (Sec. 2.3: 10 deg) */
@@ -59,7 +60,7 @@ typedef struct {
   uint32_t chain_offset;  /* global id of chain 0: chain c draws from counter (k, t, offset+c, 0) */
   int32_t chains_per_group; /* chains that share one workgroup, 0 = choose (1, 2 or 4) */
   int32_t waves_per_group;  /* wavefronts per workgroup (<= 8), 0 = choose; >= chains_per_group */
-  int32_t reserved;
+  int32_t n_global;       /* global sweeps per cycle, 0..global_every (0 means 1) */
   double sigma_end;       /* > 0: the proposal width decays geometrically from sigma to
                              sigma_end over the schedule (Sec. 2.3: 10 to 4 degrees);
                              0 = constant sigma */

@@ -20,7 +20,7 @@ class Cfg(C.Structure):
     _fields_ = [
         ("L", C.c_int32), ("n_bins", C.c_int32), ("d_min", C.c_double), ("bin_w", C.c_double),
         ("window_d", C.c_int32), ("global_every", C.c_int32), ("anchor_every", C.c_int32),
-        ("pad0", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
+        ("n_global", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
         ("total_sweeps", C.c_int64), ("seed", C.c_uint64), ("sigma_end", C.c_double),
         ("n_cascade", C.c_int32), ("cascade_d", C.c_int32 * 3),
     ]
@@ -147,7 +147,8 @@ def make_cfg(w) -> Cfg:
     """Oracle config from a synthetic.Workload."""
     casc = list(getattr(w, "cascade", ()))
     return Cfg(L=w.L, n_bins=w.n_bins, d_min=w.d_min, bin_w=w.bin_w, window_d=w.window_d,
-               global_every=w.global_every, anchor_every=w.anchor_period, pad0=0,
+               global_every=w.global_every, anchor_every=w.anchor_period,
+               n_global=getattr(w, "n_global", 1),
                sigma=w.sigma, T0=w.T0, T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed,
                sigma_end=math.radians(getattr(w, "sigma_end_deg", 0.0)), n_cascade=len(casc),
                cascade_d=(C.c_int32 * 3)(*(casc + [0] * (3 - len(casc)))))

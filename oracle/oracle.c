@@ -89,8 +89,13 @@ double oracle_beta(const oracle_cfg *cfg, int64_t t) {
   return 1.0 / T;
 }
 
+/* The last n_global sweeps of every cycle of global_every sweeps are global
+ * (Algorithm 1 alternates N_global global and N_local localized sweeps; here the
+ * localized ones come first); n_global = 0 means 1. */
 int32_t oracle_is_global(const oracle_cfg *cfg, int64_t t) {
-  return cfg->global_every > 0 && ((t + 1) % cfg->global_every) == 0;
+  if (cfg->global_every <= 0) return 0;
+  int32_t ng = cfg->n_global < 1 ? 1 : cfg->n_global;
+  return (int32_t)(t % cfg->global_every) >= cfg->global_every - ng;
 }
 
 /* Proposal width of sweep t: constant, or reduced geometrically from sigma to
@@ -388,6 +393,7 @@ void oracle_grad(const oracle_cfg *cfg, const double *y, const double *s, double
 static int cfg_ok(const oracle_cfg *cfg) {
   return cfg && cfg->L >= 2 && cfg->n_bins >= 4 && cfg->bin_w > 0.0 && cfg->window_d >= 0 &&
          cfg->global_every >= 0 && cfg->anchor_every >= 1 && cfg->T0 > 0.0 && cfg->T1 > 0.0 &&
+         cfg->n_global >= 0 && (cfg->global_every == 0 || cfg->n_global <= cfg->global_every) &&
          cfg->total_sweeps >= 1 && cfg->sigma >= 0.0 && cfg->sigma_end >= 0.0 &&
          cfg->n_cascade >= 0 && cfg->n_cascade <= 3 &&
          (cfg->n_cascade < 1 || cfg->cascade_d[0] >= 0) &&

@@ -27,9 +27,11 @@ typedef struct {
   double d_min;         /* left edge of bin 0 (A) */
   double bin_w;         /* bin width (A); knot b at d_min + bin_w*(b+0.5) */
   int32_t window_d;     /* localization radius d; window half-width h = d/2 residues */
-  int32_t global_every; /* sweep t is global iff global_every>0 && (t+1)%global_every==0 */
+  int32_t global_every; /* cycle length; sweep t is global iff global_every > 0 and
+                           t % global_every >= global_every - n_global */
   int32_t anchor_every; /* anchors after sweep t iff (t+1)%anchor_every==0; >= 1 */
-  int32_t pad0;
+  int32_t n_global;     /* global sweeps per cycle (the last n_global of every
+                           global_every sweeps); 0 means 1 */
   double sigma;         /* proposal standard deviation (rad) */
   double T0, T1;        /* geometric temperature schedule over total_sweeps */
   int64_t total_sweeps; /* S */

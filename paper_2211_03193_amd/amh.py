@@ -33,7 +33,7 @@ class AmhConfig(C.Structure):
         ("d_min", C.c_double), ("bin_w", C.c_double), ("global_every", C.c_int32),
         ("anchor_every", C.c_int32), ("sigma", C.c_double), ("T0", C.c_double), ("T1", C.c_double),
         ("total_sweeps", C.c_int64), ("seed", C.c_uint64), ("chain_offset", C.c_uint32),
-        ("chains_per_group", C.c_int32), ("waves_per_group", C.c_int32), ("reserved", C.c_int32),
+        ("chains_per_group", C.c_int32), ("waves_per_group", C.c_int32), ("n_global", C.c_int32),
         ("sigma_end", C.c_double), ("n_cascade", C.c_int32), ("cascade_d", C.c_int32 * 3),
     ]
 
@@ -145,7 +145,7 @@ def make_config(w, **over) -> AmhConfig:
                     d_min=w.d_min, bin_w=w.bin_w, global_every=w.global_every,
                     anchor_every=w.anchor_period, sigma=math.radians(w.sigma_deg), T0=w.T0,
                     T1=w.T1, total_sweeps=w.total_sweeps, seed=w.seed, chain_offset=0,
-                    chains_per_group=0, waves_per_group=0, reserved=0,
+                    chains_per_group=0, waves_per_group=0, n_global=getattr(w, "n_global", 1),
                     sigma_end=math.radians(getattr(w, "sigma_end_deg", 0.0)))
     casc = list(getattr(w, "cascade", ()))
     cfg.n_cascade = len(casc)

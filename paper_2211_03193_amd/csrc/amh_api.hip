@@ -93,6 +93,8 @@ amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
   if (!std::isfinite(c->d_min)) return sfail(AMH_E_INVAL, "d_min not finite");
   if (!(c->bin_w > 0.0) || !std::isfinite(c->bin_w)) return sfail(AMH_E_INVAL, "bin_w must be > 0");
   if (c->global_every < 0) return sfail(AMH_E_INVAL, "global_every=%d < 0", c->global_every);
+  if (c->n_global < 0 || (c->global_every > 0 && c->n_global > c->global_every))
+    return sfail(AMH_E_INVAL, "n_global=%d outside [0, global_every]", c->n_global);
   if (c->anchor_every < 1) return sfail(AMH_E_INVAL, "anchor_every=%d < 1", c->anchor_every);
   if (!(c->sigma >= 0.0) || !std::isfinite(c->sigma)) return sfail(AMH_E_INVAL, "sigma must be finite and >= 0");
   if (!(c->sigma_end >= 0.0) || !std::isfinite(c->sigma_end))
@@ -190,6 +192,7 @@ amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   for (int i = 0; i < 3; ++i) P.cascade_hw[i] = i < c.n_cascade ? c.cascade_d[i] / 2 : 0;
   P.sigma_end = c.sigma_end;
   P.global_every = c.global_every;
+  P.n_global = c.n_global < 1 ? 1 : c.n_global;
   P.anchor_every = c.anchor_every;
   P.sigma = c.sigma;
   P.T0 = c.T0;
@@ -650,8 +653,9 @@ void member_shape(const amh_ctx* x, int plan, int* G, int* W) {
 double member_cost(const amh_ctx* x) {
   const double L = x->cfg.L, h = x->cfg.window_d / 2;
   const int ge = x->cfg.global_every;
-  const double global = ge > 0 ? L * L * L / 3.0 / ge : 0.0;
-  const double local = 2.0 * L * h * (h + 1) * (ge > 0 ? 1.0 - 1.0 / ge : 1.0);
+  const double fg = ge > 0 ? (double)(x->cfg.n_global < 1 ? 1 : x->cfg.n_global) / ge : 0.0;
+  const double global = L * L * L / 3.0 * fg;
+  const double local = 2.0 * L * h * (h + 1) * (1.0 - fg);
   return global + local;
 }
 

@@ -21,7 +21,7 @@ struct SweepParams {
   float inv_w, off, tmax, d2far;
   double d_min, bin_w;
   // run
-  int L, C, half_window, global_every, anchor_every;
+  int L, C, half_window, global_every, n_global, anchor_every;   // n_global >= 1
   int n_cascade, cascade_hw[3];   // extra window half-widths taken in turn with half_window
   double sigma, sigma_end, T0, T1;  // sigma_end > 0: geometric decay of the proposal width
   int64_t S, t0, n_sweeps;

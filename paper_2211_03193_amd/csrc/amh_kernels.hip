@@ -220,6 +220,12 @@ __device__ __forceinline__ double sigma_at(const SweepParams& P, int64_t t) {
   return P.sigma;
 }
 
+// Sweep t is global iff it is one of the last n_global sweeps of its cycle of
+// global_every sweeps (Algorithm 1's alternation, localized sweeps first).
+__device__ __forceinline__ bool is_global(const SweepParams& P, int64_t t) {
+  return P.global_every > 0 && (int)((uint32_t)t % (uint32_t)P.global_every) >= P.global_every - P.n_global;
+}
+
 // Window half-width of localized sweep t: window_d, then the cascade radii in turn
 // (Sec. 2.2 allows several localization ranges).
 __device__ __forceinline__ int half_window_at(const SweepParams& P, int64_t t) {
@@ -466,7 +472,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
   bool stalled = false;
   const int64_t t_end = P.t0 + P.n_sweeps;
   for (int64_t t = P.t0; t < t_end;) {
-    const bool global = P.global_every > 0 && ((t + 1) % P.global_every) == 0;
+    const bool global = is_global(P, t);
     double T_t = P.T0;
     if (P.S > 1) T_t = P.T0 * pow(P.T1 / P.T0, (double)t / (double)(P.S - 1));
     const double beta = 1.0 / T_t;
@@ -475,7 +481,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       // the end of the launch or 4096 sweeps
       int64_t tb = t;
       while (tb < t_end && tb - t < 4096 &&
-             !(P.global_every > 0 && ((tb + 1) % P.global_every) == 0)) {
+             !is_global(P, tb)) {
         ++tb;
         if ((tb % P.anchor_every) == 0) break;
       }

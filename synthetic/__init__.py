@@ -145,6 +145,7 @@ class Workload:
     anchor_every: int = 0         # 0 -> same as global_every (or 10 when local-only)
     trace_chains: list = field(default_factory=list)
     sigma_end_deg: float = 0.0    # > 0: proposal width decays geometrically to this
+    n_global: int = 1             # global sweeps per cycle of global_every (the last ones)
     cascade: tuple = ()           # extra localization radii taken in turn with window_d
 
     @property

@@ -31,6 +31,27 @@ def test_annealed_width_and_cascade_replay(G, W):
     gu.say("variants replay G", G, "W", W)
     _, y = gu.protein(VAR)
     ctx = gu.context(VAR, y, chains_per_group=G, waves_per_group=W)
+    _replay_variant(ctx, VAR, y)
+    ctx.close()
+
+
+def test_block_of_global_sweeps_replay():
+    """Cycles of 7 sweeps whose last 4 are global (Algorithm 1's N_global block)."""
+    w = VAR.replace(global_every=7, n_global=4, anchor_every=7, total_sweeps=21)
+    gu.say("n_global replay")
+    _, y = gu.protein(w)
+    ctx = gu.context(w, y)
+    chains = [1, 4]
+    tr = gu.traced_run(ctx, chains, w.total_sweeps, chunk=5)
+    for m, c in enumerate(chains):
+        rc, rep, _ = gu.replay_chain(w, y, tr, m, c, gu.extended(w))
+        assert rc == 0 and rep["n_de_fail"] == 0 and rep["n_forks"] <= 2, rep
+    cnt = ctx.get_state()["counters"].cpu().numpy()
+    assert np.all(cnt[:, 1] > 0)          # global accepts happened
+    ctx.close()
+
+
+def _replay_variant(ctx, VAR, y):
     chains = [0, 2, 4]
     tr = gu.traced_run(ctx, chains, VAR.total_sweeps, chunk=7)
     for m, c in enumerate(chains):
@@ -47,7 +68,6 @@ def test_annealed_width_and_cascade_replay(G, W):
     key = (tr["dE"].tobytes(), tr["acc"].tobytes())
     _KEY.setdefault("ref", key)
     assert key == _KEY["ref"]
-    ctx.close()
 
 
 _KEY = {}

@@ -81,3 +81,17 @@ def test_noisy_restart_is_uniform_bounded_and_reproducible():
     assert np.all(s2 <= math.pi) and np.all(s2 > -math.pi)
     d = np.angle(np.exp(1j * (s2 - math.pi)))
     assert np.all(np.abs(d) <= a + 1e-12)
+
+
+def test_global_block_of_n_global_sweeps_per_cycle():
+    """Algorithm 1 alternates N_global global and N_local localized sweeps: with a
+    cycle of 100 and 80 global sweeps, sweeps 20..99 of every cycle are global."""
+    cfg = oracle.make_cfg(sy.CFG1.replace(global_every=100, n_global=80))
+    g = np.array([oracle.lib().oracle_is_global(oracle.C.byref(cfg), t) for t in range(300)])
+    assert g.reshape(3, 100)[:, :20].sum() == 0 and g.reshape(3, 100)[:, 20:].all()
+    one = oracle.make_cfg(sy.CFG1.replace(global_every=10, n_global=1))
+    zero = oracle.make_cfg(sy.CFG1.replace(global_every=10, n_global=0))
+    for t in range(40):
+        expect = int((t + 1) % 10 == 0)
+        assert oracle.lib().oracle_is_global(oracle.C.byref(one), t) == expect
+        assert oracle.lib().oracle_is_global(oracle.C.byref(zero), t) == expect
