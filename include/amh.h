@@ -212,9 +212,14 @@ typedef struct amh_server amh_server;
 typedef struct {
   int64_t hbm_budget_bytes; /* device bytes admitted jobs may hold (tables + chain state) */
   int32_t max_active;       /* admitted jobs at most (1 = one job at a time, in order) */
-  int32_t sweeps_per_round; /* sweeps per job per amh_server_step, >= 1 */
+  int32_t sweeps_per_round; /* R >= 1: sweeps per job per amh_server_step (see below) */
   int32_t plan;             /* launch plan of the shared launches, 0..5 (see amh_batch_tune) */
   int32_t reserved;
+  int64_t round_pairs;      /* 0: every job advances R sweeps per step.  > 0: a job whose R
+                               sweeps cost P pair evaluations (all its chains) advances
+                               R * clamp(round_pairs / P, 1, 64) sweeps, so small jobs
+                               keep pace with large ones in the shared launches.  The
+                               count depends only on the job and these options. */
 } amh_server_opts;
 
 typedef struct {
@@ -272,6 +277,12 @@ amh_status amh_batch_create(amh_ctx* const* ctxs, int32_t n, amh_batch** out);
 /* Advance every member by n_sweeps >= 0 sweeps (each member's own schedule from its
  * own sweep counter); AMH_E_INVAL if any member would pass its total_sweeps. */
 amh_status amh_batch_sweep(amh_batch* batch, int64_t n_sweeps);
+
+/* The same with a sweep count per member (n_sweeps [n members], host array, each >= 0):
+ * member i advances n_sweeps[i] sweeps in the same launches (a member with 0 sweeps
+ * only passes through).  AMH_E_INVAL, with nothing advanced, if any member would pass
+ * its total_sweeps. */
+amh_status amh_batch_sweep_each(amh_batch* batch, const int64_t* n_sweeps);
 
 /* Autotuner: time each launch plan on sweeps_per_trial real sweeps of every member
  * (they count as part of the run: 6 * sweeps_per_trial sweeps in all), keep the

@@ -54,7 +54,8 @@ def lbfgs_opts(n_iter=200, m=8, nonmonotone=5, max_ls=30, c1=1e-4, shrink=0.5, g
 
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_active", C.c_int32),
-                ("sweeps_per_round", C.c_int32), ("plan", C.c_int32), ("reserved", C.c_int32)]
+                ("sweeps_per_round", C.c_int32), ("plan", C.c_int32), ("reserved", C.c_int32),
+                ("round_pairs", C.c_int64)]
 
 
 class Job(C.Structure):
@@ -102,6 +103,7 @@ def lib():
         "amh_minimize": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
         "amh_batch_create": [C.POINTER(_P), C.c_int32, C.POINTER(_P)],
         "amh_batch_sweep": [_P, C.c_int64],
+        "amh_batch_sweep_each": [_P, C.POINTER(C.c_int64)],
         "amh_batch_tune": [_P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int32)],
         "amh_batch_set_plan": [_P, C.c_int32],
         "amh_batch_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
@@ -325,8 +327,13 @@ class Batch:
         self._h = C.c_void_p()
         check(lib().amh_batch_create(arr, len(self.members), C.byref(self._h)))
 
-    def sweep(self, n: int) -> None:
-        check(lib().amh_batch_sweep(self._h, n))
+    def sweep(self, n) -> None:
+        """n sweeps for every member, or a sequence of per-member counts."""
+        if isinstance(n, int):
+            check(lib().amh_batch_sweep(self._h, n))
+        else:
+            arr = (C.c_int64 * len(self.members))(*[int(v) for v in n])
+            check(lib().amh_batch_sweep_each(self._h, arr))
 
     def tune(self, sweeps_per_trial: int) -> tuple[int, list[float]]:
         ms = (C.c_float * self.N_PLANS)()
@@ -358,9 +365,10 @@ class Server:
     """Continuous-batching request loop (amh_server_* and amh_submit)."""
 
     def __init__(self, hbm_budget_bytes: int, max_active: int = 1 << 30, sweeps_per_round: int = 10,
-                 plan: int = 0, stream=None):
+                 plan: int = 0, round_pairs: int = 0, stream=None):
         self.opts = ServerOpts(hbm_budget_bytes=int(hbm_budget_bytes), max_active=int(max_active),
-                               sweeps_per_round=int(sweeps_per_round), plan=int(plan), reserved=0)
+                               sweeps_per_round=int(sweeps_per_round), plan=int(plan), reserved=0,
+                               round_pairs=int(round_pairs))
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         self._h = C.c_void_p()
         self._cfg = {}

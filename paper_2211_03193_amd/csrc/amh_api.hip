@@ -740,19 +740,22 @@ amh_status amh_batch_create(amh_ctx* const* ctxs, int32_t n, amh_batch** out) {
   return AMH_OK;
 }
 
-amh_status amh_batch_sweep(amh_batch* b, int64_t n_sweeps) {
+amh_status amh_batch_sweep_each(amh_batch* b, const int64_t* n_sweeps) {
   if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
-  if (n_sweeps < 0) return sfail(AMH_E_INVAL, "n_sweeps < 0");
+  if (!n_sweeps) return sfail(AMH_E_INVAL, "n_sweeps is NULL");
+  int64_t most = 0;
   for (size_t i = 0; i < b->m.size(); ++i) {
     const amh_ctx* x = b->m[i];
-    if (x->t + n_sweeps > x->cfg.total_sweeps)
+    if (n_sweeps[i] < 0) return sfail(AMH_E_INVAL, "member %zu: n_sweeps < 0", i);
+    if (x->t + n_sweeps[i] > x->cfg.total_sweeps)
       return sfail(AMH_E_INVAL, "member %zu: sweep %lld + %lld passes total_sweeps=%lld", i,
-                  (long long)x->t, (long long)n_sweeps, (long long)x->cfg.total_sweeps);
+                   (long long)x->t, (long long)n_sweeps[i], (long long)x->cfg.total_sweeps);
+    most = std::max(most, n_sweeps[i]);
   }
-  if (n_sweeps == 0) return AMH_OK;
+  if (most == 0) return AMH_OK;
   const int slot = b->ring;
   if (b->ev_used[slot]) HIP_OK(hipEventSynchronize(b->ev[slot]));
-  for (size_t i = 0; i < b->m.size(); ++i) b->h_desc[slot][i] = sweep_params(b->m[i], n_sweeps);
+  for (size_t i = 0; i < b->m.size(); ++i) b->h_desc[slot][i] = sweep_params(b->m[i], n_sweeps[i]);
   HIP_OK(hipMemcpyAsync(b->d_desc, b->h_desc[slot], sizeof(amh::SweepParams) * b->m.size(),
                         hipMemcpyHostToDevice, b->stream));
   HIP_OK(hipEventRecord(b->ev[slot], b->stream));
@@ -762,8 +765,15 @@ amh_status amh_batch_sweep(amh_batch* b, int64_t n_sweeps) {
     amh_status st = l.G == 1 ? launch_batch<1>(b, l) : l.G == 2 ? launch_batch<2>(b, l) : launch_batch<4>(b, l);
     if (st != AMH_OK) return st;
   }
-  for (auto* x : b->m) x->t += n_sweeps;
+  for (size_t i = 0; i < b->m.size(); ++i) b->m[i]->t += n_sweeps[i];
   return AMH_OK;
+}
+
+amh_status amh_batch_sweep(amh_batch* b, int64_t n_sweeps) {
+  if (!b) return sfail(AMH_E_INVAL, "batch is NULL");
+  if (n_sweeps < 0) return sfail(AMH_E_INVAL, "n_sweeps < 0");
+  std::vector<int64_t> n(b->m.size(), n_sweeps);
+  return amh_batch_sweep_each(b, n.data());
 }
 
 amh_status amh_batch_tune(amh_batch* b, int64_t sweeps_per_trial, float* ms_out, int32_t* plan_out) {

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <memory>
@@ -29,7 +30,7 @@
 
 #include "amh_error.h"
 
-static_assert(sizeof(amh_server_opts) == 24, "amh_server_opts layout");
+static_assert(sizeof(amh_server_opts) == 32, "amh_server_opts layout");
 static_assert(sizeof(amh_job) == 136, "amh_job layout");
 static_assert(sizeof(amh_job_status) == 72, "amh_job_status layout");
 
@@ -55,6 +56,7 @@ int64_t job_bytes(const amh_config& c) {
 
 struct Job {
   uint64_t id = 0;
+  int64_t chunk = 1;           // sweeps per round
   amh_config cfg{};
   std::vector<float> y;        // host copy until admission
   double target = -INFINITY;
@@ -169,6 +171,7 @@ amh_status amh_server_create(const amh_server_opts* o, void* stream, amh_server*
   if (o->max_active < 1) return sfail(AMH_E_INVAL, "max_active=%d < 1", o->max_active);
   if (o->sweeps_per_round < 1) return sfail(AMH_E_INVAL, "sweeps_per_round=%d < 1", o->sweeps_per_round);
   if (o->plan < 0 || o->plan > 5) return sfail(AMH_E_INVAL, "plan=%d outside [0, 5]", o->plan);
+  if (o->round_pairs < 0) return sfail(AMH_E_INVAL, "round_pairs < 0");
   amh_server* s = new amh_server;
   s->o = *o;
   s->stream = reinterpret_cast<hipStream_t>(stream);
@@ -191,6 +194,15 @@ amh_status amh_submit(void* server, const void* job, uint64_t* job_id) {
   j->target = jb->target;
   j->bytes = job_bytes(c);
   j->st.bytes = j->bytes;
+  j->chunk = s->o.sweeps_per_round;
+  if (s->o.round_pairs > 0) {   // pair evaluations of R sweeps of all chains of this job
+    const double L = c.L, h = c.window_d / 2;
+    const int ge = c.global_every;
+    const double fg = ge > 0 ? (double)(c.n_global < 1 ? 1 : c.n_global) / ge : 0.0;
+    const double per_sweep = (L * L * L / 3.0 * fg + 2.0 * L * h * (h + 1) * (1.0 - fg)) * c.n_chains;
+    const double k = std::floor((double)s->o.round_pairs / (per_sweep * s->o.sweeps_per_round));
+    j->chunk *= (int64_t)std::min(64.0, std::max(1.0, k));
+  }
   if (j->bytes > s->o.hbm_budget_bytes)
     return sfail(AMH_E_BUSY, "job needs %lld bytes, more than the whole budget (%lld)",
                  (long long)j->bytes, (long long)s->o.hbm_budget_bytes);
@@ -218,39 +230,28 @@ amh_status amh_server_step(amh_server* s, int32_t* n_active, int32_t* n_pending)
     if (st != AMH_OK) return st;
   }
   if (!s->active.empty()) {
-    // every active job advances sweeps_per_round sweeps (fewer at the end of its run)
-    const int64_t R = s->o.sweeps_per_round;
-    std::vector<amh_ctx*> full;
-    std::vector<uint64_t> full_ids;
+    // every active job advances its own chunk of sweeps (fewer at the end of its run)
+    std::vector<amh_ctx*> ctxs;
+    std::vector<uint64_t> ids;
+    std::vector<int64_t> nsw;
     std::vector<Job*> act;
     for (uint64_t id : s->active) {
       Job* j = s->jobs[id].get();
       act.push_back(j);
+      ctxs.push_back(j->ctx);
+      ids.push_back(id);
       const int64_t left = j->cfg.total_sweeps - j->st.sweeps;
-      if (left >= R) {
-        full.push_back(j->ctx);
-        full_ids.push_back(id);
-      }
+      nsw.push_back(std::min(left, j->chunk));
     }
-    if (full_ids != s->batch_members || (!s->batch && !full.empty())) {   // regroup the launch
+    if (ids != s->batch_members || !s->batch) {   // membership changed: regroup the launch
       drop_batch(s);
-      if (!full.empty()) {
-        if (amh_batch_create(full.data(), (int32_t)full.size(), &s->batch) != AMH_OK)
-          return lib_fail(AMH_E_DEVICE, "amh_batch_create");
-        s->batch_members = full_ids;
-        if (amh_batch_set_plan(s->batch, s->o.plan) != AMH_OK) return lib_fail(AMH_E_DEVICE, "amh_batch_set_plan");
-      }
+      if (amh_batch_create(ctxs.data(), (int32_t)ctxs.size(), &s->batch) != AMH_OK)
+        return lib_fail(AMH_E_DEVICE, "amh_batch_create");
+      s->batch_members = ids;
+      if (amh_batch_set_plan(s->batch, s->o.plan) != AMH_OK) return lib_fail(AMH_E_DEVICE, "amh_batch_set_plan");
     }
-    if (s->batch && amh_batch_sweep(s->batch, R) != AMH_OK) return lib_fail(AMH_E_DEVICE, "amh_batch_sweep");
-    for (Job* j : act) {
-      const int64_t left = j->cfg.total_sweeps - j->st.sweeps;
-      if (left < R) {
-        if (amh_sweep(j->ctx, left) != AMH_OK) return lib_fail(AMH_E_DEVICE, "amh_sweep");
-        j->st.sweeps += left;
-      } else {
-        j->st.sweeps += R;
-      }
-    }
+    if (amh_batch_sweep_each(s->batch, nsw.data()) != AMH_OK) return lib_fail(AMH_E_DEVICE, "amh_batch_sweep_each");
+    for (size_t q = 0; q < act.size(); ++q) act[q]->st.sweeps += nsw[q];
     // read back counters and energies of every active job
     size_t total = 0;
     for (Job* j : act) total += j->cfg.n_chains;

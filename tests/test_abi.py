@@ -92,7 +92,8 @@ def test_server_calls_reject_null_arguments(amh):
     assert amh.lib().amh_submit(None, None, None) == amh.E_INVAL
     h = C.c_void_p()
     assert amh.lib().amh_server_create(None, None, C.byref(h)) == amh.E_INVAL
-    for bad in (dict(hbm_budget_bytes=0), dict(max_active=0), dict(sweeps_per_round=0), dict(plan=6)):
+    for bad in (dict(hbm_budget_bytes=0), dict(max_active=0), dict(sweeps_per_round=0), dict(plan=6),
+                dict(round_pairs=-1)):
         o = amh.ServerOpts(hbm_budget_bytes=1 << 30, max_active=4, sweeps_per_round=10, plan=0)
         for k, v in bad.items():
             setattr(o, k, v)
@@ -105,11 +106,12 @@ def test_server_calls_reject_null_arguments(amh):
     assert amh.lib().amh_batch_create(arr, 1, C.byref(h)) == amh.E_INVAL
     assert amh.lib().amh_batch_create(arr, 0, C.byref(h)) == amh.E_INVAL
     assert amh.lib().amh_batch_sweep(None, 1) == amh.E_INVAL
+    assert amh.lib().amh_batch_sweep_each(None, None) == amh.E_INVAL
     assert amh.lib().amh_batch_destroy(None) == amh.OK
 
 
 def test_server_struct_layouts(amh):
-    assert C.sizeof(amh.ServerOpts) == 24
+    assert C.sizeof(amh.ServerOpts) == 32 and amh.ServerOpts.round_pairs.offset == 24
     assert C.sizeof(amh.Job) == 120 + 8 + 8 and amh.Job.target.offset == 128
     assert C.sizeof(amh.JobStatus) == 72 and amh.JobStatus.best_V.offset == 24
 

@@ -83,6 +83,26 @@ def test_batch_equals_plain_launches(tables, alone12, plan):
         c.close()
 
 
+def test_per_member_sweep_counts(tables):
+    from paper_2211_03193_amd import amh
+    gu.say("batch per-member counts")
+    counts = [12, 0, 7, 3]
+    ctxs = [gu.context(w, y) for w, y in zip(MEMBERS, tables)]
+    b = amh.Batch(ctxs)
+    b.sweep(counts)
+    for (w, y), ctx, n in zip(zip(MEMBERS, tables), ctxs, counts):
+        ref = gu.context(w, y)
+        ref.sweep(n)
+        _equal(_state(ctx), _state(ref))
+        ref.close()
+    with pytest.raises(amh.AmhError):
+        b.sweep([100, 0, 0, 0])      # member 0 would pass its 80 sweeps
+    assert [c.info()["t"] for c in ctxs] == counts
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
 def test_traced_member_replays(tables):
     from paper_2211_03193_amd import amh
     gu.say("batch traced member")

@@ -58,11 +58,14 @@ def _serve(jobs, **opts):
     return res
 
 
-def test_same_result_alone_and_in_the_mix():
-    gu.say("serve mix vs alone")
+@pytest.mark.parametrize("round_pairs", [0, 3_000_000])
+def test_same_result_alone_and_in_the_mix(round_pairs):
+    gu.say("serve mix vs alone, round_pairs", round_pairs)
     jobs = _jobs()
-    mix = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=4, sweeps_per_round=5)
-    alone = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=1, sweeps_per_round=5)
+    mix = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=4, sweeps_per_round=5,
+                 round_pairs=round_pairs)
+    alone = _serve(jobs, hbm_budget_bytes=64 << 20, max_active=1, sweeps_per_round=5,
+                   round_pairs=round_pairs)
     for (w, *_), a, b in zip(jobs, mix, alone):
         assert a["state"] == b["state"] == 2
         assert a["sweeps"] == b["sweeps"] and a["sweeps_to_target"] == b["sweeps_to_target"]
@@ -70,8 +73,10 @@ def test_same_result_alone_and_in_the_mix():
         assert np.array_equal(a["v"], b["v"])
         assert a["best_V"] == b["best_V"] == a["v"][:, 1].min()
         assert a["t_submit"] <= a["t_admit"] <= a["t_done"]
-    # the easy target ends its job at the first anchor; the others run to their last sweep
-    assert mix[2]["reached"] == 1 and mix[2]["sweeps_to_target"] == 5 and mix[2]["sweeps"] == 5
+    # the easy target is reached at the first anchor and ends its job with that round
+    # (one round of R sweeps, or the job's own larger chunk with round_pairs)
+    assert mix[2]["reached"] == 1 and mix[2]["sweeps_to_target"] == 5
+    assert mix[2]["sweeps"] == 5 if round_pairs == 0 else mix[2]["sweeps"] % 5 == 0
     for k in (0, 1, 3, 4, 5):
         if not mix[k]["reached"]:
             assert mix[k]["sweeps"] == jobs[k][0].total_sweeps
