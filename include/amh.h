@@ -122,6 +122,12 @@ amh_status amh_set_state(amh_ctx* ctx, const double* s_dev, const double* s_best
  * index are kept.  amplitude >= 0 (rad); use a new tag for every restart. */
 amh_status amh_perturb(amh_ctx* ctx, double amplitude, uint32_t tag);
 
+/* Bound on the wait of a pipelined localized sweep for the previous sweep's progress
+ * (1 <= polls <= 2^24, the default; each poll sleeps ~128 cycles).  A wait that runs
+ * out gives up instead of hanging, flags the context, and the next amh_poll returns
+ * AMH_E_DEVICE; the chains' state is then undefined.  For testing the error path. */
+amh_status amh_set_wait_bound(amh_ctx* ctx, int32_t polls);
+
 /* Time-to-target: the first anchor with V <= target records its sweep count in
  * counters[c][2] (default target: -infinity, never reached). */
 amh_status amh_set_target(amh_ctx* ctx, double target);

@@ -95,6 +95,7 @@ def lib():
         "amh_set_state": [_P, _P, _P, _P, _P, _P, C.c_int64],
         "amh_set_target": [_P, C.c_double],
         "amh_perturb": [_P, C.c_double, C.c_uint32],
+        "amh_set_wait_bound": [_P, C.c_int32],
         "amh_set_trace": [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, C.c_int64, _P, C.c_int64],
         "amh_poll": [_P],
         "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -264,6 +265,9 @@ class Context:
 
     def set_target(self, target: float) -> None:
         check(lib().amh_set_target(self._h, target))
+
+    def set_wait_bound(self, polls: int) -> None:
+        check(lib().amh_set_wait_bound(self._h, polls))
 
     def perturb(self, amplitude: float, tag: int) -> None:
         """Noisy restart of every chain (amh_perturb): uniform in [-amplitude, amplitude] rad."""

@@ -77,6 +77,7 @@ struct amh_ctx {
   int64_t trace_cap = 0, trace_t0 = 0;
   double* tr_anchor = nullptr;
   int64_t trace_anchor_cap = 0, trace_anchor0 = 0;
+  int spin_limit = 1 << 24;   // bound of the pipelined sweeps' waits (amh_set_wait_bound)
   // L-BFGS workspace, grown on demand
   double* work = nullptr;
   size_t work_n = 0;
@@ -203,6 +204,7 @@ amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   P.key0 = (uint32_t)c.seed;
   P.key1 = (uint32_t)(c.seed >> 32);
   P.chain_offset = c.chain_offset;
+  P.spin_limit = x->spin_limit;
   P.target = x->target;
   P.s = x->s;
   P.s_best = x->s_best;
@@ -417,6 +419,13 @@ amh_status amh_perturb(amh_ctx* x, double amplitude, uint32_t tag) {
   P.s_best = x->s_best;
   P.keep_best = 1;
   return launch_conf(P, c.n_chains, x->stream);
+}
+
+amh_status amh_set_wait_bound(amh_ctx* x, int32_t polls) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (polls < 1 || polls > (1 << 24)) return sfail(AMH_E_INVAL, "polls=%d outside [1, 2^24]", polls);
+  x->spin_limit = polls;
+  return AMH_OK;
 }
 
 amh_status amh_set_target(amh_ctx* x, double target) {

@@ -26,6 +26,7 @@ struct SweepParams {
   double sigma, sigma_end, T0, T1;  // sigma_end > 0: geometric decay of the proposal width
   int64_t S, t0, n_sweeps;
   uint32_t key0, key1, chain_offset;
+  int spin_limit;     // polls of a pipelined localized sweep's wait before it gives up
   double target;
   // chain state
   double* s;          // [C][2L]

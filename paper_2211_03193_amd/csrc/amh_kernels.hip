@@ -279,7 +279,7 @@ struct Pipe {
 __device__ __forceinline__ bool wait_progress(const SweepParams& P, const int* ctr, int target,
                                               bool& stalled) {
   if (stalled) return false;
-  for (int spin = 0; spin < (1 << 24); ++spin) {
+  for (int spin = 0; spin < P.spin_limit; ++spin) {
     if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
     __builtin_amdgcn_s_sleep(2);
   }

@@ -232,3 +232,27 @@ def test_edge_cases_replay(case):
         local = [t for t in range(30) if (t + 1) % w.global_every != 0]
         assert np.all(acc[local] == 1)
     ctx.close()
+
+
+def test_wait_bound_reports_a_device_error():
+    """A one-poll bound on the pipelined localized sweeps' wait makes them give up;
+    the launch still ends and amh_poll reports the failure (error path forced from
+    the host; nothing hangs)."""
+    from paper_2211_03193_amd import amh
+    gu.say("wait bound")
+    w = SMALL.replace(global_every=0, total_sweeps=20, anchor_every=10, window_d=12, L=40)
+    _, y = gu.protein(w)
+    ctx = gu.context(w, y, chains_per_group=1, waves_per_group=4)
+    with pytest.raises(amh.AmhError) as e:
+        ctx.set_wait_bound(0)
+    assert e.value.status == amh.E_INVAL
+    ctx.set_wait_bound(1)
+    ctx.sweep(10)
+    with pytest.raises(amh.AmhError) as e:
+        ctx.poll()
+    assert e.value.status == amh.E_DEVICE
+    ctx.close()
+    ok = gu.context(w, y, chains_per_group=1, waves_per_group=4)
+    ok.sweep(10)
+    ok.poll()
+    ok.close()
