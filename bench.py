@@ -406,6 +406,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=495)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--chains", type=int, default=0,
+                    help="chains of the single-protein workload (default 1024; 128 is one GPU's "
+                         "share when 1024 chains are split over 8 GPUs)")
     ap.add_argument("--chains-per-group", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=800,
@@ -455,6 +458,8 @@ def main():
             print(json.dumps(out), flush=True)
         return
     w = sy.CFG2
+    if args.chains:
+        w = w.replace(n_chains=args.chains, name=f"single-L300-{args.chains}chains")
     cyc = w.global_every
     if (args.warmup + args.steps) * cyc > w.total_sweeps:
         sys.exit(f"warmup + steps must fit the {w.total_sweeps}-sweep schedule "
@@ -487,8 +492,10 @@ def main():
         "pair_evals_per_s": pairs_step * args.steps / r["wall"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED,
-                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch (HBM)",
-                     "kernel": "sweep_kernel<4>", "avg_launch_ms": launch_s * 1e3,
+                     "traffic": measured_traffic() if w.name == sy.CFG2.name else None,
+                     "traffic_unit": "bytes per launch (HBM)",
+                     "kernel": f"sweep_kernel<{r['info']['chains_per_group']}>",
+                     "avg_launch_ms": launch_s * 1e3,
                      "flops_per_pair": flops_pair, "pairs_per_launch": pairs_step},
         "energy": {"V_ref": r["V_ref"], "target": r["target"],
                    "best_min": float(r["v"][:, 1].min()), "best_median": float(np.median(r["v"][:, 1])),
