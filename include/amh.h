@@ -32,7 +32,7 @@ typedef enum {
   AMH_E_NOMEM = -2,       /* device allocation failed */
   AMH_E_DEVICE = -3,      /* HIP runtime error */
   AMH_E_NUMERIC = -4,     /* non-finite table entry, energy or energy change */
-  AMH_E_UNSUPPORTED = -5, /* call not provided by this build */
+  AMH_E_UNSUPPORTED = -5, /* call or option not provided by this library version */
   AMH_E_BUSY = -6         /* request cannot be admitted now (serving) */
 } amh_status;
 
@@ -143,7 +143,7 @@ amh_status amh_set_trace(amh_ctx* ctx, int32_t n, const int32_t* chain_ids, doub
                          double* anchor_dev, int64_t anchor_capacity);
 
 /* Philox4x32-10 blocks, the counter-based generator behind every proposal (Sec. 2.4
- * names an RNG per chain; this build draws proposal k of sweep t of chain c from
+ * names an RNG per chain; proposal k of sweep t of chain c is drawn from
  * the counter (k, t, c, 0)): out_dev[i][0..3] = Philox(ctr_dev[i][0..3], key) for
  * n blocks of four uint32 words; key low word first. */
 amh_status amh_philox(const uint32_t* ctr_dev, int64_t n, uint64_t key, uint32_t* out_dev,
