@@ -195,11 +195,17 @@ struct Lds {
   __device__ long long* nacc(int W) const {
     return reinterpret_cast<long long*>(prog(W) + ((G * W + 1) & ~1));
   }
+  // per-wavefront queue of 64 near pairs of a global proposal (row, column, chain, d^2)
+  __device__ uint2* qbuf(int W, int wave) const {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(nacc(W) + W);
+    return reinterpret_cast<uint2*>((a + 15) & ~(uintptr_t)15) + 64 * wave;
+  }
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
   return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
-         8 * (size_t)G + 4 * (size_t)((G * W + 1) & ~1) + 8 * (size_t)W + 64;
+         8 * (size_t)G + 4 * (size_t)((G * W + 1) & ~1) + 8 * (size_t)W + 64 + 16 +
+         8 * 64 * (size_t)W;
 }
 
 __device__ __forceinline__ void axis_atoms(const double* x64, int k, D3& A, D3& B) {
@@ -549,67 +555,88 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
           // each thread owns a column j (its trial C-beta in registers) and a segment
           // of the rows i < p; the fixed C-beta x_i are read from LDS, the same i for
           // the lanes of a segment.  Pairs farther apart than the last knot add 0.
+          // Pairs inside it are queued in a per-wavefront LDS buffer (ballot and
+          // lane rank give each its slot) and evaluated 64 at a time, one per lane, so
+          // the few lanes whose columns lie next to the pivot (where most near pairs
+          // are) no longer hold up the whole wavefront.
           const int nseg = M >= T ? 1 : T / M;
           const int seglen = (p + nseg - 1) / nseg;
-          for (int item = tid; item < nseg * M; item += T) {
-            const int sgi = item / M, jj = item - sgi * M, j = p + jj;
-            const int ib = sgi * seglen, ie = ib + seglen < p ? ib + seglen : p;
-            float tx[G], ty[G], tz[G];
+          // items (segment-major: neighbouring items are neighbouring columns) are dealt
+          // to the wavefronts round-robin, so the columns next to the pivot, which hold
+          // most near pairs, are spread over every wavefront; at most one per thread
+          const int item = (tid & 63) * W + (tid >> 6);
+          const bool has = item < nseg * M;
+          const int sgi = has ? item / M : 0, jj = has ? item - sgi * M : 0, j = p + jj;
+          const int ib = sgi * seglen, ie = has ? (ib + seglen < p ? ib + seglen : p) : ib;
+          float tx[G], ty[G], tz[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-              if (g < nact) {
-                const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
-                tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
-              } else {
-                tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
-              }
+          for (int g = 0; g < G; ++g) {
+            if (g < nact && has) {
+              const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
+              tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
+            } else {
+              tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
             }
-            // a pair inside the last knot issues its table load and leaves it pending;
-            // it is consumed at the lane's next near pair or after the loop, so the
-            // wavefront does not wait on the load where it was issued
-            bool pend = false;
-            float4 py = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            float pf = 0.0f;
-            int pg = 0;
-            // NR rows per step: the NR * G broadcast reads are issued together, the
-            // distance test is branch-free and one branch covers the NR rows
-            constexpr int NR = G >= 4 ? 2 : 4;
-            for (int i0 = ib; i0 < ie; i0 += NR) {
-              float d2[NR][G];
-              bool any = false;
-#pragma unroll
-              for (int u = 0; u < NR; ++u) {
-                const int i = i0 + u < ie ? i0 + u : ie - 1;
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                  const float4 xi = S.w32(g)[i];
-                  const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
-                  const float q = dx * dx + dy * dy + dz * dz;
-                  d2[u][g] = i0 + u < ie ? q : 3.0e38f;
-                  any |= d2[u][g] < P.d2far;
-                }
-              }
-              if (any) {
-#pragma unroll
-                for (int u = 0; u < NR; ++u) {
-                  const float* row = P.ydev + (size_t)pair_row(i0 + u, j, L) * P.stride;
-#pragma unroll
-                  for (int g = 0; g < G; ++g) {
-                    if (d2[u][g] < P.d2far) {
-                      if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
-                      int b;
-                      spline_pos(__builtin_amdgcn_sqrtf(d2[u][g]), sp, b, pf);
-                      const float* q = row + b;
-                      py = make_float4(q[0], q[1], q[2], q[3]);
-                      pg = g;
-                      pend = true;
-                    }
-                  }
-                }
-              }
-            }
-            if (pend) add_chain<G>(acc, pg, (double)catmull_rom(py.x, py.y, py.z, py.w, pf));
           }
+          uint2* const qb = S.qbuf(W, wave);
+          int fill = 0;   // entries in the wavefront's buffer (uniform over the wave)
+          // evaluate the first n queued pairs, one per lane
+          auto flush = [&](int nq) {
+            wave_sync();
+            if (lane < nq) {
+              const uint2 e = qb[lane];
+              const int qi = (int)(e.x & 1023u), qj = (int)((e.x >> 10) & 1023u), qg = (int)(e.x >> 20);
+              int bin;
+              float f;
+              spline_pos(__builtin_amdgcn_sqrtf(__uint_as_float(e.y)), sp, bin, f);
+              const float* row = P.ydev + (size_t)pair_row(qi, qj, L) * P.stride + bin;
+              add_chain<G>(acc, qg, (double)catmull_rom(row[0], row[1], row[2], row[3], f));
+            }
+            wave_sync();
+          };
+          // NR rows per step: the NR * G broadcast reads are issued together and the
+          // distance test is branch-free; the step count is the same for every lane
+          constexpr int NR = G >= 4 ? 2 : 4;
+          for (int r0 = 0; r0 < seglen; r0 += NR) {
+            float d2[NR][G];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+              const int i = ib + r0 + u;
+              const int ic = i < ie ? i : (ie > ib ? ie - 1 : 0);
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const float4 xi = S.w32(g)[ic];
+                const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
+                const float q = dx * dx + dy * dy + dz * dz;
+                d2[u][g] = i < ie ? q : 3.0e38f;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const bool near = d2[u][g] < P.d2far;
+                const unsigned long long bal = __ballot(near);
+                if (bal == 0ull) continue;
+                const int cs = (int)__popcll(bal);
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                    (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
+                const uint2 e = make_uint2((unsigned int)(ib + r0 + u) | ((unsigned int)j << 10) |
+                                               ((unsigned int)g << 20),
+                                           __float_as_uint(d2[u][g]));
+                const int room = 64 - fill;
+                if (near && rank < room) qb[fill + rank] = e;
+                if (cs >= room) {          // the buffer is full: evaluate it, keep the rest
+                  flush(64);
+                  if (near && rank >= room) qb[rank - room] = e;
+                  fill = cs - room;
+                } else {
+                  fill += cs;
+                }
+              }
+            }
+          }
+          if (fill > 0) flush(fill);
         }
         if (k & 1) {
           for (int x = tid; x < L - 1; x += T) {
