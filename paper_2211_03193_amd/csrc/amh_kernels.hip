@@ -426,6 +426,14 @@ __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int
   __syncthreads();
 }
 
+// A pair's deviation energy rounded to a multiple of 2^-30: the rectangle sums of
+// a global sweep (|sum| < 2^23) are then exact in float64 whatever the order of
+// the additions, so every launch shape, batch and lane assignment carries the same
+// value (the rounding, < 1e-9 per pair, is far inside the parity tolerance).
+__device__ __forceinline__ double fixed30(float x) {
+  return rint((double)x * 1073741824.0) * (1.0 / 1073741824.0);
+}
+
 // acc[g] += v for a lane-varying chain index g (kept in registers).
 template <int G>
 __device__ __forceinline__ void add_chain(double* acc, int g, double v) {
@@ -561,23 +569,6 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
           // are) no longer hold up the whole wavefront.
           const int nseg = M >= T ? 1 : T / M;
           const int seglen = (p + nseg - 1) / nseg;
-          // items (segment-major: neighbouring items are neighbouring columns) are dealt
-          // to the wavefronts round-robin, so the columns next to the pivot, which hold
-          // most near pairs, are spread over every wavefront; at most one per thread
-          const int item = (tid & 63) * W + (tid >> 6);
-          const bool has = item < nseg * M;
-          const int sgi = has ? item / M : 0, jj = has ? item - sgi * M : 0, j = p + jj;
-          const int ib = sgi * seglen, ie = has ? (ib + seglen < p ? ib + seglen : p) : ib;
-          float tx[G], ty[G], tz[G];
-#pragma unroll
-          for (int g = 0; g < G; ++g) {
-            if (g < nact && has) {
-              const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
-              tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
-            } else {
-              tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
-            }
-          }
           uint2* const qb = S.qbuf(W, wave);
           int fill = 0;   // entries in the wavefront's buffer (uniform over the wave)
           // evaluate the first n queued pairs, one per lane
@@ -590,48 +581,69 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
               float f;
               spline_pos(__builtin_amdgcn_sqrtf(__uint_as_float(e.y)), sp, bin, f);
               const float* row = P.ydev + (size_t)pair_row(qi, qj, L) * P.stride + bin;
-              add_chain<G>(acc, qg, (double)catmull_rom(row[0], row[1], row[2], row[3], f));
+              add_chain<G>(acc, qg, fixed30(catmull_rom(row[0], row[1], row[2], row[3], f)));
             }
             wave_sync();
           };
-          // NR rows per step: the NR * G broadcast reads are issued together and the
-          // distance test is branch-free; the step count is the same for every lane
-          constexpr int NR = G >= 4 ? 2 : 4;
-          for (int r0 = 0; r0 < seglen; r0 += NR) {
-            float d2[NR][G];
+          // items (segment-major: neighbouring items are neighbouring columns) are dealt
+          // to the wavefronts round-robin, so the columns next to the pivot, which hold
+          // most near pairs, are spread over every wavefront; a thread takes one item
+          // per round, and every thread runs every round (the queue is per wavefront)
+          const int nitems = nseg * M;
+          for (int base = 0; base < nitems; base += T) {
+            const int item = base + (tid & 63) * W + (tid >> 6);
+            const bool has = item < nitems;
+            const int sgi = has ? item / M : 0, jj = has ? item - sgi * M : 0, j = p + jj;
+            const int ib = sgi * seglen, ie = has ? (ib + seglen < p ? ib + seglen : p) : ib;
+            float tx[G], ty[G], tz[G];
 #pragma unroll
-            for (int u = 0; u < NR; ++u) {
-              const int i = ib + r0 + u;
-              const int ic = i < ie ? i : (ie > ib ? ie - 1 : 0);
-#pragma unroll
-              for (int g = 0; g < G; ++g) {
-                const float4 xi = S.w32(g)[ic];
-                const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
-                const float q = dx * dx + dy * dy + dz * dz;
-                d2[u][g] = i < ie ? q : 3.0e38f;
+            for (int g = 0; g < G; ++g) {
+              if (g < nact && has) {
+                const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
+                tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
+              } else {
+                tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
               }
             }
+            // NR rows per step: the NR * G broadcast reads are issued together and the
+            // distance test is branch-free; the step count is the same for every lane
+            constexpr int NR = G >= 4 ? 2 : 4;
+            for (int r0 = 0; r0 < seglen; r0 += NR) {
+              float d2[NR][G];
 #pragma unroll
-            for (int u = 0; u < NR; ++u) {
+              for (int u = 0; u < NR; ++u) {
+                const int i = ib + r0 + u;
+                const int ic = i < ie ? i : (ie > ib ? ie - 1 : 0);
 #pragma unroll
-              for (int g = 0; g < G; ++g) {
-                const bool near = d2[u][g] < P.d2far;
-                const unsigned long long bal = __ballot(near);
-                if (bal == 0ull) continue;
-                const int cs = (int)__popcll(bal);
-                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                    (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
-                const uint2 e = make_uint2((unsigned int)(ib + r0 + u) | ((unsigned int)j << 10) |
-                                               ((unsigned int)g << 20),
-                                           __float_as_uint(d2[u][g]));
-                const int room = 64 - fill;
-                if (near && rank < room) qb[fill + rank] = e;
-                if (cs >= room) {          // the buffer is full: evaluate it, keep the rest
-                  flush(64);
-                  if (near && rank >= room) qb[rank - room] = e;
-                  fill = cs - room;
-                } else {
-                  fill += cs;
+                for (int g = 0; g < G; ++g) {
+                  const float4 xi = S.w32(g)[ic];
+                  const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
+                  const float q = dx * dx + dy * dy + dz * dz;
+                  d2[u][g] = i < ie ? q : 3.0e38f;
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < NR; ++u) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                  const bool near = d2[u][g] < P.d2far;
+                  const unsigned long long bal = __ballot(near);
+                  if (bal == 0ull) continue;
+                  const int cs = (int)__popcll(bal);
+                  const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                      (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
+                  const uint2 e = make_uint2((unsigned int)(ib + r0 + u) | ((unsigned int)j << 10) |
+                                                 ((unsigned int)g << 20),
+                                             __float_as_uint(d2[u][g]));
+                  const int room = 64 - fill;
+                  if (near && rank < room) qb[fill + rank] = e;
+                  if (cs >= room) {          // the buffer is full: evaluate it, keep the rest
+                    flush(64);
+                    if (near && rank >= room) qb[rank - room] = e;
+                    fill = cs - room;
+                  } else {
+                    fill += cs;
+                  }
                 }
               }
             }
@@ -648,8 +660,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
 #pragma unroll
             for (int g = 0; g < G; ++g)
               if (g < nact)
-                tr[g] += sgn * (double)edev32(row, dist2_64(ld3(atom(S.x64(g), i, 3)),
-                                                            ld3(atom(S.x64(g), j, 3))), sp, P.d2far);
+                tr[g] += sgn * fixed30(edev32(row, dist2_64(ld3(atom(S.x64(g), i, 3)),
+                                                            ld3(atom(S.x64(g), j, 3))), sp, P.d2far));
           }
         }
 #pragma unroll

@@ -151,6 +151,29 @@ def test_wide_rectangles_use_every_wave(G, W):
 _WIDE = {}
 
 
+@pytest.mark.parametrize("G,W", [(1, 1), (1, 4), (4, 8)])
+def test_compact_start_with_more_columns_than_threads(G, W):
+    """From the folded reference conformation (long-range contacts everywhere), a
+    global proposal with more moved columns than workgroup threads (L = 160 at 64
+    or 256 threads) must still evaluate every column: replayed by the oracle."""
+    gu.say("compact wide G", G, "W", W)
+    s_ref, y = gu.protein(WIDE)
+    s0 = np.tile(s_ref, (WIDE.n_chains, 1))
+    ctx = gu.context(WIDE, y, s0=s0, chains_per_group=G, waves_per_group=W)
+    chains = [0, 4]
+    tr = gu.traced_run(ctx, chains, 4)
+    ctx.close()
+    for m, c in enumerate(chains):
+        rc, rep, _ = gu.replay_chain(WIDE, y, tr, m, c, s_ref)
+        assert rc == 0 and rep["n_de_fail"] == 0 and rep["n_forks"] <= 2, rep
+    key = (tr["dE"].tobytes(), tr["acc"].tobytes())
+    _COMPACT.setdefault("ref", key)
+    assert key == _COMPACT["ref"]
+
+
+_COMPACT = {}
+
+
 def test_resume_is_bit_exact():
     gu.say("resume")
     _, y = gu.protein(SMALL)
