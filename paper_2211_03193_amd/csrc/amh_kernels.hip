@@ -178,7 +178,8 @@ __global__ void conf_energy_kernel(ConfParams P) {
 // LDS layout of a sweep workgroup: per chain (stride 128 L bytes) the float64
 // atoms [L][4][3], the float32 pivot-relative C-beta work array [L] and the
 // torsions [2L]; then the rotation slots of the current and next proposal per
-// chain, the wavefront partials and the anchor scratch.
+// chain, the wavefront partials, the anchor scratch, the near-pair queues and the
+// bounding spheres of the rectangle's tiles.
 struct Lds {
   unsigned char* base;
   int L, G;
@@ -200,12 +201,16 @@ struct Lds {
     const uintptr_t a = reinterpret_cast<uintptr_t>(nacc(W) + W);
     return reinterpret_cast<uint2*>((a + 15) & ~(uintptr_t)15) + 64 * wave;
   }
+  // bounding spheres (centroid, radius) of the blocks of 8 residues of chain g
+  __device__ float4* sph(int W, int g) const {
+    return reinterpret_cast<float4*>(qbuf(W, W)) + g * ((L + 7) >> 3);
+  }
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
   return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
          8 * (size_t)G + 4 * (size_t)((G * W + 1) & ~1) + 8 * (size_t)W + 64 + 16 +
-         8 * 64 * (size_t)W;
+         8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8);
 }
 
 __device__ __forceinline__ void axis_atoms(const double* x64, int k, D3& A, D3& B) {
@@ -527,6 +532,10 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       for (int g = 0; g < G; ++g) Rp[g] = 0.0;
       Batch bt{};
       D3 nA{0, 0, 0}, nU{0, 0, 1};   // owner: pivot point and axis of proposal k+1
+      // blocks of 8 residues for the rectangle's tiles; a tile is skipped when its
+      // spheres are more than rcut apart (the last knot + 0.05 A)
+      const int nb8 = (L + 7) >> 3, nres8 = 8 * nb8;
+      const float rcut = __builtin_amdgcn_sqrtf(P.d2far) + 0.05f;
       if (owner) {
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
         D3 a, b;
@@ -540,12 +549,37 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       for (int k = 0; k < n; ++k) {
         const int c = k >> 1, p = (k & 1) ? c + 1 : c, M = L - p;
         const Rot* pr = S.par() + (k & 1) * G;
-        // [B] float32 C-beta of the fixed residues i < p relative to the pivot point
-        for (int e = tid; e < nact * p; e += T) {
-          const int g = e / p, r = e - g * p;
-          const Rot& R = pr[g];
-          const D3 x = ld3(atom(S.x64(g), r, 3));
-          S.w32(g)[r] = make_float4((float)(x.x - R.a[0]), (float)(x.y - R.a[1]), (float)(x.z - R.a[2]), 0.0f);
+        // [B] float32 C-beta of the trial conformation relative to the pivot point
+        // (the fixed residues i < p as they are, the moved ones rotated) and a
+        // bounding sphere (centroid, radius) of every block of 8 consecutive residues;
+        // the 8 residues of a block sit in 8 aligned lanes of one wavefront
+        for (int e0 = 0; e0 < nact * nres8; e0 += T) {
+          const int e = e0 + tid, g = e / nres8, r = e - g * nres8;
+          const bool real = g < nact && r < L;
+          float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+          if (real) {
+            const Rot& R = pr[g];
+            const D3 x = ld3(atom(S.x64(g), r, 3));
+            if (r < p) {
+              vx = (float)(x.x - R.a[0]); vy = (float)(x.y - R.a[1]); vz = (float)(x.z - R.a[2]);
+            } else {
+              const D3 v = rot_rel(R, x);
+              vx = (float)v.x; vy = (float)v.y; vz = (float)v.z;
+            }
+            S.w32(g)[r] = make_float4(vx, vy, vz, 0.0f);
+          }
+          float cnt = real ? 1.0f : 0.0f, cx = vx, cy = vy, cz = vz;
+#pragma unroll
+          for (int o = 1; o < 8; o <<= 1) {
+            cx += __shfl_xor(cx, o); cy += __shfl_xor(cy, o); cz += __shfl_xor(cz, o);
+            cnt += __shfl_xor(cnt, o);
+          }
+          const float inv = 1.0f / (cnt > 1.0f ? cnt : 1.0f);
+          cx *= inv; cy *= inv; cz *= inv;
+          float rad = real ? sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) + (vz - cz) * (vz - cz)) : 0.0f;
+#pragma unroll
+          for (int o = 1; o < 8; o <<= 1) rad = fmaxf(rad, __shfl_xor(rad, o));
+          if (g < nact && (r & 7) == 0) S.sph(W, g)[r >> 3] = make_float4(cx, cy, cz, rad);
         }
         if (owner && k + 1 < n) {
           D3 nB;
@@ -560,15 +594,14 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         for (int g = 0; g < G; ++g) { acc[g] = 0.0; tr[g] = 0.0; }
         const int npairs = p * M;
         if (npairs > 0) {
-          // each thread owns a column j (its trial C-beta in registers) and a segment
-          // of the rows i < p; the fixed C-beta x_i are read from LDS, the same i for
-          // the lanes of a segment.  Pairs farther apart than the last knot add 0.
-          // Pairs inside it are queued in a per-wavefront LDS buffer (ballot and
-          // lane rank give each its slot) and evaluated 64 at a time, one per lane, so
-          // the few lanes whose columns lie next to the pivot (where most near pairs
-          // are) no longer hold up the whole wavefront.
-          const int nseg = M >= T ? 1 : T / M;
-          const int seglen = (p + nseg - 1) / nseg;
+          // The rectangle is cut into tiles of 8 rows (blocks I up to that of p - 1) by 8
+          // columns (blocks J from that of p) of every chain.  A tile whose bounding
+          // spheres lie farther apart than the last knot (plus a margin far above
+          // float32 rounding) holds only pairs beyond it, which add exactly 0, and is
+          // skipped whole.  Candidate tiles are dealt to the wavefronts round-robin; a
+          // surviving tile is one wavefront step, a pair per lane.  Pairs inside the
+          // last knot are queued in a per-wavefront LDS buffer (ballot and lane rank
+          // give each its slot) and evaluated 64 at a time, one per lane.
           uint2* const qb = S.qbuf(W, wave);
           int fill = 0;   // entries in the wavefront's buffer (uniform over the wave)
           // evaluate the first n queued pairs, one per lane
@@ -585,66 +618,48 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
             }
             wave_sync();
           };
-          // items (segment-major: neighbouring items are neighbouring columns) are dealt
-          // to the wavefronts round-robin, so the columns next to the pivot, which hold
-          // most near pairs, are spread over every wavefront; a thread takes one item
-          // per round, and every thread runs every round (the queue is per wavefront)
-          const int nitems = nseg * M;
-          for (int base = 0; base < nitems; base += T) {
-            const int item = base + (tid & 63) * W + (tid >> 6);
-            const bool has = item < nitems;
-            const int sgi = has ? item / M : 0, jj = has ? item - sgi * M : 0, j = p + jj;
-            const int ib = sgi * seglen, ie = has ? (ib + seglen < p ? ib + seglen : p) : ib;
-            float tx[G], ty[G], tz[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-              if (g < nact && has) {
-                const D3 v = rot_rel(pr[g], ld3(atom(S.x64(g), j, 3)));
-                tx[g] = (float)v.x; ty[g] = (float)v.y; tz[g] = (float)v.z;
-              } else {
-                tx[g] = 1e18f; ty[g] = 1e18f; tz[g] = 1e18f;
-              }
+          const int Ip = (p - 1) >> 3, Jp = p >> 3, nJ = nb8 - Jp, per = (Ip + 1) * nJ;
+          const int ncand = nact * per;
+          const int lr = lane >> 3, lc = lane & 7;
+          for (int base = 0; base < ncand; base += T) {
+            const int cand = base + lane * W + wave;
+            int code = 0;
+            bool keep = false;
+            if (cand < ncand) {
+              const int g = cand / per, rem = cand - g * per, I = rem / nJ, J = Jp + (rem - I * nJ);
+              const float4 a = S.sph(W, g)[I], b = S.sph(W, g)[J];
+              const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+              const float lim = rcut + a.w + b.w;
+              keep = dx * dx + dy * dy + dz * dz <= lim * lim;
+              code = (g << 16) | (I << 8) | J;
             }
-            // NR rows per step: the NR * G broadcast reads are issued together and the
-            // distance test is branch-free; the step count is the same for every lane
-            constexpr int NR = G >= 4 ? 2 : 4;
-            for (int r0 = 0; r0 < seglen; r0 += NR) {
-              float d2[NR][G];
-#pragma unroll
-              for (int u = 0; u < NR; ++u) {
-                const int i = ib + r0 + u;
-                const int ic = i < ie ? i : (ie > ib ? ie - 1 : 0);
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                  const float4 xi = S.w32(g)[ic];
-                  const float dx = tx[g] - xi.x, dy = ty[g] - xi.y, dz = tz[g] - xi.z;
-                  const float q = dx * dx + dy * dy + dz * dz;
-                  d2[u][g] = i < ie ? q : 3.0e38f;
-                }
-              }
-#pragma unroll
-              for (int u = 0; u < NR; ++u) {
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                  const bool near = d2[u][g] < P.d2far;
-                  const unsigned long long bal = __ballot(near);
-                  if (bal == 0ull) continue;
-                  const int cs = (int)__popcll(bal);
-                  const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                      (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
-                  const uint2 e = make_uint2((unsigned int)(ib + r0 + u) | ((unsigned int)j << 10) |
-                                                 ((unsigned int)g << 20),
-                                             __float_as_uint(d2[u][g]));
-                  const int room = 64 - fill;
-                  if (near && rank < room) qb[fill + rank] = e;
-                  if (cs >= room) {          // the buffer is full: evaluate it, keep the rest
-                    flush(64);
-                    if (near && rank >= room) qb[rank - room] = e;
-                    fill = cs - room;
-                  } else {
-                    fill += cs;
-                  }
-                }
+            unsigned long long m = __ballot(keep);
+            while (m) {
+              const int l = __builtin_ctzll(m);
+              m &= m - 1;
+              const int cd = __builtin_amdgcn_readlane(code, l);
+              const int g = cd >> 16, i = 8 * ((cd >> 8) & 255) + lr, j = 8 * (cd & 255) + lc;
+              const bool ok = i < p && j >= p && j < L;
+              const float4 xi = S.w32(g)[i < L ? i : L - 1], xj = S.w32(g)[j < L ? j : L - 1];
+              const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+              const float q = dx * dx + dy * dy + dz * dz;
+              const float d2 = ok ? q : 3.0e38f;
+              const bool near = d2 < P.d2far;
+              const unsigned long long bal = __ballot(near);
+              if (bal == 0ull) continue;
+              const int cs = (int)__popcll(bal);
+              const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                  (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
+              const uint2 e = make_uint2((unsigned int)i | ((unsigned int)j << 10) | ((unsigned int)g << 20),
+                                         __float_as_uint(d2));
+              const int room = 64 - fill;
+              if (near && rank < room) qb[fill + rank] = e;
+              if (cs >= room) {          // the buffer is full: evaluate it, keep the rest
+                flush(64);
+                if (near && rank >= room) qb[rank - room] = e;
+                fill = cs - room;
+              } else {
+                fill += cs;
               }
             }
           }
