@@ -167,6 +167,27 @@ __device__ __forceinline__ float edev32(const float* __restrict__ dev_row, float
   return d2 < d2far ? spline32(dev_row, __builtin_amdgcn_sqrtf(d2), S) : 0.0f;
 }
 
+// The same, split in two so that the loads can be issued well before the value is
+// needed: the stencil of a squared distance (zeros beyond the last knot, which
+// evaluate to exactly 0), then its evaluation.
+struct Stencil {
+  float y0, y1, y2, y3, f;
+};
+__device__ __forceinline__ Stencil fetch_dev(const float* __restrict__ dev_row, float d2,
+                                             const Spline32& S, float d2far) {
+  Stencil s{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (d2 < d2far) {
+    int b;
+    spline_pos(__builtin_amdgcn_sqrtf(d2), S, b, s.f);
+    const float* q = dev_row + b;
+    s.y0 = q[0]; s.y1 = q[1]; s.y2 = q[2]; s.y3 = q[3];
+  }
+  return s;
+}
+__device__ __forceinline__ float eval_dev(const Stencil& s) {
+  return catmull_rom(s.y0, s.y1, s.y2, s.y3, s.f);
+}
+
 __device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,
                                            double d_min, double w) {
   const double t = (d - (d_min + 0.5 * w)) / w;
@@ -209,11 +230,6 @@ __device__ __forceinline__ void nerf_place(const double* A, const double* B, con
 
 // ---------------------------------------------------------------------------
 // Wavefront helpers (wave64).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // DPP move of both halves of a double (row_mask, bank_mask all set, bound_ctrl on).
 template <int CTRL>
@@ -226,6 +242,25 @@ constexpr int kDppXor1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRor4 = 0x124;  // row_ror:4 (lane i of a row reads lane i-4 mod 16)
 constexpr int kDppRor8 = 0x128;  // row_ror:8
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane i of each 8 reads lane 7 - i
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum and maximum over each aligned group of 8 lanes; every lane of a group gets the
+// same value (the two operands of each addition are the same in both partners).
+__device__ __forceinline__ float sum8(float v) {
+  v += dpp_f<kDppXor1>(v);
+  v += dpp_f<kDppXor2>(v);
+  return v + dpp_f<kDppHalfMirror>(v);
+}
+__device__ __forceinline__ float max8(float v) {
+  v = fmaxf(v, dpp_f<kDppXor1>(v));
+  v = fmaxf(v, dpp_f<kDppXor2>(v));
+  return fmaxf(v, dpp_f<kDppHalfMirror>(v));
+}
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);

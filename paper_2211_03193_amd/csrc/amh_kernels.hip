@@ -341,22 +341,40 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain
     const int npair = nF * nM;
     double dE = 0.0;
     Rot R;
+    // the first 64 changed pairs, one per lane: the stencil of the current distance is
+    // fetched before the rotation is set up, so that the two overlap
+    const bool mine = live && lane < npair;
+    D3 xi{0, 0, 0}, xj{0, 0, 0};
+    const float* row = P.ydev;
+    Stencil s0{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (mine) {
+      // lane = a nM + b; the float quotient is exact for lane < 64 (the fraction stays
+      // at least 0.5 / nM away from an integer)
+      const int a = (int)(((float)lane + 0.5f) / (float)nM), ii = lo + a, j = p + (lane - a * nM);
+      xi = ld3(atom(x64, ii, 3));
+      xj = ld3(atom(x64, j, 3));
+      row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
+      s0 = fetch_dev(row, dist2_64(xi, xj), sp, P.d2far);
+    }
     if (live) {
       D3 a, b;
       axis_atoms(x64, k, a, b);
       make_rot(a, b, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
       if (npair > 0) {
         double part = 0.0;
-        for (int x = lane; x < npair; x += 64) {
+        if (mine) {
+          const float e1 = edev32(row, dist2_64(xi, apply_rot(R, xj)), sp, P.d2far);
+          part = (double)e1 - (double)eval_dev(s0);
+        }
+        for (int x = lane + 64; x < npair; x += 64) {   // windows wider than 64 pairs
           const int ii = lo + x / nM, j = p + x % nM;
-          const D3 xi = ld3(atom(x64, ii, 3)), xj = ld3(atom(x64, j, 3));
-          const D3 xt = apply_rot(R, xj);
-          const float* row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
-          const float e0 = edev32(row, dist2_64(xi, xj), sp, P.d2far);
-          const float e1 = edev32(row, dist2_64(xi, xt), sp, P.d2far);
+          const D3 yi = ld3(atom(x64, ii, 3)), yj = ld3(atom(x64, j, 3));
+          const float* r2 = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
+          const float e0 = edev32(r2, dist2_64(yi, yj), sp, P.d2far);
+          const float e1 = edev32(r2, dist2_64(yi, apply_rot(R, yj)), sp, P.d2far);
           part += (double)e1 - (double)e0;
         }
-        dE = wave_sum(part);
+        dE = wave_sum_dpp(part);
       }
     }
     const int acc = (dE <= 0.0) || (log_u < -beta * dE);
@@ -568,17 +586,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
             }
             S.w32(g)[r] = make_float4(vx, vy, vz, 0.0f);
           }
-          float cnt = real ? 1.0f : 0.0f, cx = vx, cy = vy, cz = vz;
-#pragma unroll
-          for (int o = 1; o < 8; o <<= 1) {
-            cx += __shfl_xor(cx, o); cy += __shfl_xor(cy, o); cz += __shfl_xor(cz, o);
-            cnt += __shfl_xor(cnt, o);
-          }
-          const float inv = 1.0f / (cnt > 1.0f ? cnt : 1.0f);
-          cx *= inv; cy *= inv; cz *= inv;
-          float rad = real ? sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) + (vz - cz) * (vz - cz)) : 0.0f;
-#pragma unroll
-          for (int o = 1; o < 8; o <<= 1) rad = fmaxf(rad, __shfl_xor(rad, o));
+          const float cnt = sum8(real ? 1.0f : 0.0f), inv = 1.0f / (cnt > 1.0f ? cnt : 1.0f);
+          const float cx = sum8(vx) * inv, cy = sum8(vy) * inv, cz = sum8(vz) * inv;
+          const float rad = max8(real ? sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) +
+                                              (vz - cz) * (vz - cz))
+                                      : 0.0f);
           if (g < nact && (r & 7) == 0) S.sph(W, g)[r >> 3] = make_float4(cx, cy, cz, rad);
         }
         if (owner && k + 1 < n) {
