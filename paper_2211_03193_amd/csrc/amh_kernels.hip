@@ -197,9 +197,10 @@ struct Lds {
     return reinterpret_cast<long long*>(prog(W) + ((G * W + 1) & ~1));
   }
   // per-wavefront queue of 64 near pairs of a global proposal (row, column, chain, d^2)
+  // (offsets from base, not integer addresses, so that the compiler keeps LDS accesses)
   __device__ uint2* qbuf(int W, int wave) const {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(nacc(W) + W);
-    return reinterpret_cast<uint2*>((a + 15) & ~(uintptr_t)15) + 64 * wave;
+    const size_t o = (size_t)(reinterpret_cast<unsigned char*>(nacc(W) + W) - base);
+    return reinterpret_cast<uint2*>(base + ((o + 15) & ~(size_t)15)) + 64 * wave;
   }
   // bounding spheres (centroid, radius) of the blocks of 8 residues of chain g
   __device__ float4* sph(int W, int g) const {
