@@ -27,19 +27,29 @@ PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9    # FLOP/s: 256 CUs x 64 lanes x FMA
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_L300_1024chains_traffic.json")
 
 
+def code_digest(paths) -> str:
+    """sha256 over the given C++/HIP sources with comments and whitespace removed, so
+    that a change of the code, not of its comments, changes the digest."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for p in paths:
+        text = open(os.path.join(ROOT, p), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the sweep kernel from the committed counter record
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None once the kernel sources no
-    longer hash to the ones the counters were taken on."""
-    import hashlib
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None once the kernel code differs
+    from the code the counters were taken on."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
-        h = hashlib.sha256()
-        for s in rec["sources"]:
-            h.update(open(os.path.join(ROOT, s), "rb").read())
+        if code_digest(rec["sources"]) != rec["code_sha256"]:
+            return None
     except (OSError, ValueError, KeyError):
-        return None
-    if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 

@@ -24,6 +24,9 @@
 //     proposal (the new rectangle sum on accept, an O(L) row/column update when
 //     p advances), so each global proposal evaluates one spline per changed near
 //     pair instead of two;
+//   * the rectangle is walked in 8 x 8 tiles (blocks of 8 residues); a tile whose
+//     two bounding spheres lie farther apart than the last knot holds only pairs
+//     that add zero and is skipped whole, a decision uniform over the wavefront;
 //   * the proposal randoms come from Philox4x32-10 at counter (k, t, chain, 0),
 //     the same stream the oracle replays, drawn 64 proposals at a time, one per lane;
 //   * the master coordinates (N, CA, C, C-beta) live in LDS in float64 and are
