@@ -242,6 +242,9 @@ constexpr int kDppXor1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRor4 = 0x124;  // row_ror:4 (lane i of a row reads lane i-4 mod 16)
 constexpr int kDppRor8 = 0x128;  // row_ror:8
+constexpr int kDppShl4 = 0x104;  // row_shl:4 (lane i of a row reads lane i+4; 0 past the row's end)
+constexpr int kDppShl8 = 0x108;  // row_shl:8
+constexpr int kDppShr4 = 0x114;  // row_shr:4 (lane i of a row reads lane i-4; 0 before its start)
 constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane i of each 8 reads lane 7 - i
 
 template <int CTRL>

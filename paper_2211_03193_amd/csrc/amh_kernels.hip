@@ -552,6 +552,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       double Rp[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) Rp[g] = 0.0;
+      double rp = 0.0;   // W = 4 or 8: chain g's carried rectangle energy in lane ls(g)
       Batch bt{};
       D3 nA{0, 0, 0}, nU{0, 0, 1};   // owner: pivot point and axis of proposal k+1
       // blocks of 8 residues for the rectangle's tiles; a tile is skipped when its
@@ -715,27 +716,45 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         }
         unsigned int accmask = 0;
         double dE_own = 0.0;
+        if (W == 4 || W == 8) {
+          // the chains' decisions side by side: lane ls(g) = off + 2 W g gathers chain
+          // g's new rectangle sum and transition term by DPP (the same additions, in
+          // the same order up to commutation, as summing the W partials in turn) and
+          // takes the decision; a ballot collects them
+          const int off = W == 8 ? 4 : 0, stride = 2 * W;
+          double snew = part, trn;
+          if (W == 8) {
+            snew += dpp_d<kDppShr4>(part);   // lane 16g+4: waves 4-7 + waves 0-3
+            trn = dpp_d<kDppShl8>(snew);     // from lane 16g+12
+          } else {
+            trn = dpp_d<kDppShl4>(part);     // from lane 8g+4
+          }
+          const int gl = (lane - off) / stride;
+          const bool dec = lane >= off && ((lane - off) % stride) == 0 && gl < nact;
+          const double lu = dec ? pr[gl].log_u : 0.0;
+          if (dec) rp += trn;
+          const double dE = npairs > 0 ? snew - rp : 0.0;
+          const bool a = dec && ((dE <= 0.0) || (lu < -beta * dE));
+          if (a) rp = npairs > 0 ? snew : 0.0;
+          const unsigned long long bal = __ballot(a);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if (g < nact) {
-            double Snew = 0.0, Tr = 0.0;
-            if (W == 4) {
-              Snew = readlane_d(part, (2 * g) * W);
-              Tr = readlane_d(part, (2 * g + 1) * W);
-            } else if (W == 8) {
-              Snew = readlane_d(part, (2 * g) * W) + readlane_d(part, (2 * g) * W + 4);
-              Tr = readlane_d(part, (2 * g + 1) * W) + readlane_d(part, (2 * g + 1) * W + 4);
-            } else {
+          for (int g = 0; g < G; ++g) accmask |= (unsigned int)((bal >> (off + stride * g)) & 1ull) << g;
+          if (owner) dE_own = readlane_d(dE, off + stride * wave);
+        } else {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            if (g < nact) {
+              double Snew = 0.0, Tr = 0.0;
               for (int v = 0; v < W; ++v) {
                 Snew += readlane_d(part, (2 * g) * W + v);
                 Tr += readlane_d(part, (2 * g + 1) * W + v);
               }
+              Rp[g] += Tr;
+              const double dE = npairs > 0 ? Snew - Rp[g] : 0.0;
+              const int a = (dE <= 0.0) || (pr[g].log_u < -beta * dE);
+              if (a) { accmask |= 1u << g; Rp[g] = npairs > 0 ? Snew : 0.0; }
+              if (g == wave) dE_own = dE;
             }
-            Rp[g] += Tr;
-            const double dE = npairs > 0 ? Snew - Rp[g] : 0.0;
-            const int a = (dE <= 0.0) || (pr[g].log_u < -beta * dE);
-            if (a) { accmask |= 1u << g; Rp[g] = npairs > 0 ? Snew : 0.0; }
-            if (g == wave) dE_own = dE;
           }
         }
         if (owner) {
