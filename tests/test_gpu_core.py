@@ -173,6 +173,27 @@ def test_compact_start_with_more_columns_than_threads(G, W):
 
 _COMPACT = {}
 
+LONGEST = sy.Workload("longest", L=1024, n_chains=2, total_sweeps=2, window_d=12, global_every=2,
+                      sigma_deg=10.0, T0=1.0, T1=0.5, seed=0x5EED03, protein_seed=10, noise_seed=11)
+
+
+def test_longest_chain_replays():
+    """L = 1024, the longest chain the library takes (10-bit residue indices in the
+    near-pair queue, 128 blocks of 8 residues), from the folded reference
+    conformation: a localized and a global sweep of both chains replayed by the
+    oracle."""
+    gu.say("longest chain L=1024")
+    s_ref, y = gu.protein(LONGEST)
+    s0 = np.tile(s_ref, (LONGEST.n_chains, 1))
+    ctx = gu.context(LONGEST, y, s0=s0)
+    chains = [0, 1]
+    tr = gu.traced_run(ctx, chains, 2)
+    ctx.close()
+    for m, c in enumerate(chains):
+        gu.say("replay chain", c)
+        rc, rep, _ = gu.replay_chain(LONGEST, y, tr, m, c, s_ref)
+        assert rc == 0 and rep["n_de_fail"] == 0 and rep["n_logic_fail"] == 0 and rep["n_forks"] <= 2, rep
+
 
 def test_resume_is_bit_exact():
     gu.say("resume")
