@@ -59,7 +59,9 @@ typedef struct {
   uint64_t seed;          /* Philox4x32-10 key (low word, high word) */
   uint32_t chain_offset;  /* global id of chain 0: chain c draws from counter (k, t, offset+c, 0) */
   int32_t chains_per_group; /* chains that share one workgroup, 0 = choose (1, 2 or 4) */
-  int32_t waves_per_group;  /* wavefronts per workgroup (<= 8), 0 = choose; >= chains_per_group */
+  int32_t waves_per_group;  /* wavefronts per workgroup (<= 8), >= chains_per_group; 0 = choose:
+                               8 when the grid has at most one workgroup per compute unit,
+                               else 2 * chains_per_group (at least 4) */
   int32_t n_global;       /* global sweeps per cycle, 0..global_every (0 means 1) */
   double sigma_end;       /* > 0: the proposal width decays geometrically from sigma to
                              sigma_end over the schedule (Sec. 2.3: 10 to 4 degrees);

@@ -85,7 +85,8 @@ struct amh_ctx {
 
 namespace {
 
-amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
+// n_cu: compute units of the device (for the automatic launch shape).
+amh_status validate(const amh_config* c, int n_cu, int* G, int* W, size_t* lds) {
   if (!c) return sfail(AMH_E_INVAL, "config is NULL");
   if (c->L < 2 || c->L > 1024) return sfail(AMH_E_INVAL, "L=%d outside [2, 1024]", c->L);
   if (c->n_chains < 1) return sfail(AMH_E_INVAL, "n_chains=%d < 1", c->n_chains);
@@ -120,7 +121,14 @@ amh_status validate(const amh_config* c, int* G, int* W, size_t* lds) {
                      amh::sweep_lds_bytes(g, c->L, w ? w : (2 * g > 4 ? 2 * g : 4)) > kMaxLds))
       g >>= 1;
   }
-  if (w == 0) w = 2 * g > 4 ? 2 * g : 4;
+  if (w == 0) {
+    // eight waves (two per SIMD, the most the register budget allows) when the grid
+    // gives each workgroup a compute unit of its own, else 2G (at least 4) so that
+    // two workgroups share a compute unit
+    const int64_t grid = ((int64_t)c->n_chains + g - 1) / g;
+    w = 2 * g > 4 ? 2 * g : 4;
+    if (grid <= n_cu && amh::sweep_lds_bytes(g, c->L, 8) <= kMaxLds) w = 8;
+  }
   if (w < g) return sfail(AMH_E_INVAL, "waves_per_group=%d < chains_per_group=%d", w, g);
   const size_t need = amh::sweep_lds_bytes(g, c->L, w);
   if (need > kMaxLds)
@@ -243,7 +251,11 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   *out = nullptr;
   int G = 0, W = 0;
   size_t lds = 0;
-  amh_status st = validate(cfg, &G, &W, &lds);
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+    n_cu = 256;
+  amh_status st = validate(cfg, n_cu, &G, &W, &lds);
   if (st != AMH_OK) return st;
   if (!y_dev) return sfail(AMH_E_INVAL, "distogram table is NULL");
   amh_ctx* x = new amh_ctx;
