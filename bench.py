@@ -299,7 +299,6 @@ def variants_leg(samples, chains):
         ctx.close()
         return {"best": v}
     timed("3_alt_mh", alt)
-    timed("4_lbfgs_noisy_restarts", lambda: variants.lbfgs_noisy_restarts(w, y, batches=samples // 100))
 
     def col5():
         # its localized-MH phases (20 sweeps per batch of 100 samples) anneal over their own run

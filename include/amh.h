@@ -64,7 +64,7 @@ typedef struct {
                                else 2 * chains_per_group (at least 4) */
   int32_t n_global;       /* global sweeps per cycle, 0..global_every (0 means 1) */
   double sigma_end;       /* > 0: the proposal width decays geometrically from sigma to
-                             sigma_end over the schedule (Sec. 2.3: 10 to 4 degrees);
+                             sigma_end over the schedule (Sec. 2.3, Sec. 3: 10 to 4 deg);
                              0 = constant sigma */
   int32_t n_cascade;      /* extra localization radii, 0..3 (Sec. 2.2: cascaded ranges): */
   int32_t cascade_d[3];   /* localized sweep t uses window_d if t % (1 + n_cascade) == 0,

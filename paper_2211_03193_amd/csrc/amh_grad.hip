@@ -2,7 +2,7 @@
 // and a per-chain L-BFGS minimiser built on it, for MI355X (gfx950, wave64).
 //
 // The energy is V(s) = sum_{i<j} E_ij(|CB_i - CB_j|) over the conformation G(s)
-// (the AlphaFold1 distogram term the paper samples, Sec. 2.2).  Turning torsion k
+// (the AlphaFold1 distogram term the paper samples, Sec. 2.3).  Turning torsion k
 // by eps rotates every residue from the pivot p on about the bond axis u through
 // the point a (N_c -> CA_c for phi_c, CA_c -> C_c for psi_c), so with the C-beta
 // forces F_j = dV/dx_j

@@ -228,7 +228,7 @@ struct Batch {  // proposal randoms of 64 consecutive proposals, one per lane
 };
 
 // Proposal width of sweep t: constant, or reduced geometrically from sigma to
-// sigma_end over the schedule (Sec. 2.3 reduces it from 10 to 4 degrees).
+// sigma_end over the schedule (Sec. 2.3 and Sec. 3 reduce it from 10 to 4 degrees).
 __device__ __forceinline__ double sigma_at(const SweepParams& P, int64_t t) {
   if (P.sigma_end > 0.0 && P.sigma > 0.0 && P.S > 1)
     return P.sigma * pow(P.sigma_end / P.sigma, (double)t / (double)(P.S - 1));

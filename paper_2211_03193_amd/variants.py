@@ -14,10 +14,11 @@ proposal, energy and restart runs on the device.  Energies are in nats.
 * ``beta_sweep`` -- Alt-MH and plain MH at fixed beta over a range of beta, many
   independent runs each (Fig. 5);
 * ``chain_count_study`` -- the best energy found by few and by many chains
-  (Fig. 4C);
-* ``lbfgs_noisy_restarts`` -- L-BFGS in batches of 100 iterations with noisy
-  restarts between them (the fourth scheme of Sec. 3; the fifth, L-BFGS with
-  localized MH, is ``hybrid.lbfgs_with_localized_mh``).
+  (Fig. 4C).
+
+The fourth scheme of Sec. 3, L-BFGS with noisy restarts, is one of the paper's
+comparison systems and is not built; the fifth, L-BFGS interleaved with
+localized MH, is ``hybrid.lbfgs_with_localized_mh``.
 """
 from __future__ import annotations
 
@@ -125,24 +126,5 @@ def summary_gain(a: float, b: float) -> float:
     return (b - a) / abs(b) if b else float("nan")
 
 
-def lbfgs_noisy_restarts(w, y: torch.Tensor, batches: int, iters: int = 100,
-                         amplitude_deg: float = 10.0, opts: amh.LbfgsOpts | None = None) -> dict:
-    """L-BFGS in batches of `iters` iterations with a noisy restart between batches
-    (the fourth scheme of Sec. 3); the chains start from the extended chain."""
-    ctx = _ctx(w, y)
-    base = opts or amh.lbfgs_opts()
-    o = amh.LbfgsOpts(**{f: getattr(base, f) for f, _ in amh.LbfgsOpts._fields_})
-    o.n_iter = iters
-    for b in range(batches):
-        ctx.minimize(None, o)
-        if b + 1 < batches:
-            ctx.perturb(math.radians(amplitude_deg), b)
-    Vb, _, _ = ctx.energy(which=1)
-    ctx.poll()
-    out = {"best": float(Vb.min()), "batches": batches}
-    ctx.close()
-    return out
-
-
 __all__ = ["alt_mh_restarts", "mh_noisy_restarts", "beta_sweep", "chain_count_study",
-           "lbfgs_noisy_restarts", "summary_gain"]
+           "summary_gain"]

@@ -13,7 +13,7 @@ import synthetic as sy
 
 pytestmark = pytest.mark.gpu
 
-gu = pytest.importorskip("gpu_util")
+import gpu_util as gu  # noqa: E402  (an import error fails the run)
 
 
 @pytest.fixture(autouse=True)

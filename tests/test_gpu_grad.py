@@ -19,7 +19,7 @@ import synthetic as sy
 
 pytestmark = pytest.mark.gpu
 
-gu = pytest.importorskip("gpu_util")
+import gpu_util as gu  # noqa: E402  (an import error fails the run)
 EPS = np.finfo(np.float64).eps
 
 
@@ -39,7 +39,7 @@ def _grad_tol(L, s, g_or):
     return 64.0 * L * EPS * R * (np.abs(g_or).max() + 1.0)
 
 
-@pytest.mark.parametrize("L", [2, 3, 17, 64, 300])
+@pytest.mark.parametrize("L", [2, 3, 17, 64, 300, 400])
 def test_grad_matches_oracle(L):
     gu.say("grad L", L)
     w = sy.CFG1.replace(L=L, protein_seed=L + 3, noise_seed=L + 4)
@@ -62,6 +62,29 @@ def test_grad_matches_oracle(L):
         assert g[b, 0] == 0.0 and g[b, -1] == 0.0
     gu.say("grad L", L, "worst err / tol", worst)
     ctx.close()
+
+
+def test_grad_L400_512_conformations_sampled():
+    """The differentiation workload's launch: 512 conformations of a 400-residue
+    protein in one amh_grad call; four of them checked against the oracle."""
+    L, B = 400, 512
+    gu.say("grad L", L, "B", B)
+    w = sy.CFG1.replace(L=L, n_chains=B, protein_seed=L + 5, noise_seed=L + 6)
+    s_ref, y = gu.protein(w)
+    rng = np.random.default_rng(L)
+    s = s_ref[None, :] + 0.3 * rng.standard_normal((B, 2 * L))
+    s = np.ascontiguousarray(np.mod(s + np.pi, 2 * np.pi) - np.pi)
+    ctx = gu.context(w.replace(n_chains=1), y)
+    V, g = ctx.grad(torch.from_numpy(s).to(gu.DEV))
+    V, g = V.cpu().numpy(), g.cpu().numpy()
+    ctx.close()
+    assert np.isfinite(V).all() and np.isfinite(g).all()
+    cfg = oracle.make_cfg(w)
+    y32 = y.astype(np.float32).astype(np.float64)
+    for b in (0, 170, 341, 511):
+        Vo, go = oracle.grad(cfg, y32, s[b])
+        assert V[b] == pytest.approx(Vo, rel=1e-12)
+        assert np.abs(g[b] - go).max() <= _grad_tol(L, s[b], go)
 
 
 def test_grad_of_current_chains_and_finite_differences():
