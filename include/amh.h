@@ -205,6 +205,24 @@ amh_status amh_minimize(amh_ctx* ctx, double* s_dev, int32_t B, const amh_lbfgs_
                         double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
                         double* f_trace_dev, double* x_trace_dev);
 
+/* amh_minimize for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels
+ * and results, but the float64 workspace is the library's fixed scratch array
+ * (8 Mi doubles = 64 MiB per device, held from the library's load until the process
+ * ends; its device address is looked up once per device by amh_init).  The call
+ * allocates nothing and calls no allocating routine.
+ *   Arguments, layouts and outputs are those of amh_minimize.
+ *   B (5 + 2m) 2L must not exceed 8,388,608 (e.g. B <= 499 at L = 400, m = 8),
+ *   else AMH_E_INVAL and nothing is launched.
+ * Every call on one device shares that device's scratch array (the workspace is
+ * written before it is read, so no clearing is needed): calls that overlap on one
+ * GPU (two streams, two host threads, or two contexts) race and give undefined
+ * results; order them on one stream or synchronise between them. */
+amh_status amh_minimize_noalloc(amh_ctx* ctx, double* s_dev, int32_t B,
+                                const amh_lbfgs_opts* opts, double* V_out_dev,
+                                int32_t* iters_out_dev, int32_t* status_out_dev,
+                                double* f_trace_dev, double* x_trace_dev);
+
 /* ---- Serving: a continuous-batching request loop --------------------------------
  * Folding jobs (one protein each) are queued by amh_submit and admitted in arrival
  * order while a slot is free and the device memory they need fits the budget.

@@ -102,6 +102,7 @@ def lib():
                      C.POINTER(C.c_int64)],
         "amh_grad": [_P, _P, C.c_int32, _P, _P],
         "amh_minimize": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
+        "amh_minimize_noalloc": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
         "amh_batch_create": [C.POINTER(_P), C.c_int32, C.POINTER(_P)],
         "amh_batch_sweep": [_P, C.c_int64],
         "amh_batch_sweep_each": [_P, C.POINTER(C.c_int64)],
@@ -220,9 +221,11 @@ class Context:
         return V, g
 
     def minimize(self, s: torch.Tensor | None = None, opts: LbfgsOpts | None = None,
-                 trace: bool = False, iterates: bool = False) -> dict:
-        """L-BFGS on V (amh_minimize).  s [B][2L] is minimised in place; with s None the
-        context's current chains are (and their V, best state and coordinates follow)."""
+                 trace: bool = False, iterates: bool = False, no_alloc: bool = False) -> dict:
+        """L-BFGS on V (amh_minimize, or amh_minimize_noalloc with no_alloc: the
+        library's fixed scratch as workspace).  s [B][2L] is minimised in place; with s
+        None the context's current chains are (and their V, best state and coordinates
+        follow)."""
         self._check_s(s)
         opts = opts or lbfgs_opts()
         B = self.C if s is None else s.shape[0]
@@ -235,9 +238,9 @@ class Context:
                "x": torch.full((B, opts.n_iter + 1, 2 * self.L), float("nan"), dtype=torch.float64,
                                device=d) if iterates else None}
         if B > 0:   # an empty tensor has no address; NULL would mean the context's chains
-            check(lib().amh_minimize(self._h, _ptr(s), B, C.byref(opts), _ptr(out["V"]),
-                                     _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["trace"]),
-                                     _ptr(out["x"])))
+            fn = lib().amh_minimize_noalloc if no_alloc else lib().amh_minimize
+            check(fn(self._h, _ptr(s), B, C.byref(opts), _ptr(out["V"]), _ptr(out["iters"]),
+                     _ptr(out["status"]), _ptr(out["trace"]), _ptr(out["x"])))
         return out
 
     def energy_fn(self):

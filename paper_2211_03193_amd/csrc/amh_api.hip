@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -81,7 +82,38 @@ struct amh_ctx {
   // L-BFGS workspace, grown on demand
   double* work = nullptr;
   size_t work_n = 0;
+  // this device's copy of the library's fixed scratch array (amh_minimize_noalloc)
+  double* scratch = nullptr;
 };
+
+// Fixed scratch of amh_minimize_noalloc: the L-BFGS workspace of callers that cannot
+// allocate.  Each device holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns for the current
+// device (the array's name in host code is not a device address).
+static __device__ __align__(256) double scratch[amh::kNoallocScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[amh::kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current), looked up
+// once per device and kept.
+amh_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= amh::kMaxDevices) return sfail(AMH_E_DEVICE, "device %d outside [0, %d)", dev, amh::kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return sfail(AMH_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return AMH_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -241,6 +273,95 @@ amh_status read_err(amh_ctx* x, unsigned int* out) {
 
 }  // namespace
 
+namespace {
+
+// amh_minimize (workspace owned by the context, grown with hipMalloc) and
+// amh_minimize_noalloc (workspace = this device's fixed scratch array).
+amh_status minimize_impl(amh_ctx* x, double* s_dev, int32_t B, const amh_lbfgs_opts* o,
+                         double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
+                         double* f_trace_dev, double* x_trace_dev, bool no_alloc) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (!o) return sfail(AMH_E_INVAL, "opts is NULL");
+  if (B < 0) return sfail(AMH_E_INVAL, "B < 0");
+  if (!s_dev && B != x->cfg.n_chains)
+    return sfail(AMH_E_INVAL, "B=%d must equal n_chains=%d when s is NULL", B, x->cfg.n_chains);
+  if (o->n_iter < 0) return sfail(AMH_E_INVAL, "n_iter=%d < 0", o->n_iter);
+  if (o->m < 1 || o->m > amh::kLbfgsMaxHistory)
+    return sfail(AMH_E_INVAL, "m=%d outside [1, %d]", o->m, amh::kLbfgsMaxHistory);
+  if (o->nonmonotone < 1 || o->nonmonotone > amh::kLbfgsMaxNonmonotone)
+    return sfail(AMH_E_INVAL, "nonmonotone=%d outside [1, %d]", o->nonmonotone, amh::kLbfgsMaxNonmonotone);
+  if (o->max_ls < 1) return sfail(AMH_E_INVAL, "max_ls=%d < 1", o->max_ls);
+  if (!(o->c1 > 0.0 && o->c1 < 1.0)) return sfail(AMH_E_INVAL, "c1 must lie in (0, 1)");
+  if (!(o->shrink > 0.0 && o->shrink < 1.0)) return sfail(AMH_E_INVAL, "shrink must lie in (0, 1)");
+  if (!(o->gtol >= 0.0) || !std::isfinite(o->gtol)) return sfail(AMH_E_INVAL, "gtol must be finite and >= 0");
+  if (!(o->step0 > 0.0) || !std::isfinite(o->step0)) return sfail(AMH_E_INVAL, "step0 must be finite and > 0");
+  if (B == 0) return AMH_OK;
+  const int L = x->cfg.L;
+  const size_t need = amh::lbfgs_work_doubles(L, o->m) * (size_t)B;
+  double* work = x->work;
+  if (no_alloc) {
+    if (need > (size_t)amh::kNoallocScratchDoubles)
+      return sfail(AMH_E_INVAL,
+                   "B=%d conformations of L=%d with m=%d need %zu workspace doubles; the fixed "
+                   "scratch holds %lld (B (5 + 2m) 2L <= %lld)", B, L, o->m, need,
+                   (long long)amh::kNoallocScratchDoubles, (long long)amh::kNoallocScratchDoubles);
+    if (!x->scratch) return sfail(AMH_E_DEVICE, "the scratch array has no device address");
+    work = x->scratch;
+  } else if (need > x->work_n) {
+    HIP_OK(hipStreamSynchronize(x->stream));
+    (void)hipFree(x->work);
+    x->work = nullptr;
+    x->work_n = 0;
+    amh_status st = dev_alloc(&x->work, need);
+    if (st != AMH_OK) return st;
+    x->work_n = need;
+    work = x->work;
+  }
+  amh::LbfgsParams P{};
+  P.L = L;
+  P.s = s_dev ? s_dev : x->s;
+  P.table = x->table;
+  P.stride = x->stride;
+  P.nb = x->cfg.n_bins;
+  P.d_min = x->cfg.d_min;
+  P.bin_w = x->cfg.bin_w;
+  P.n_iter = o->n_iter;
+  P.m = o->m;
+  P.nonmonotone = o->nonmonotone;
+  P.max_ls = o->max_ls;
+  P.c1 = o->c1;
+  P.shrink = o->shrink;
+  P.gtol = o->gtol;
+  P.step0 = o->step0;
+  P.work = work;
+  P.V = V_out_dev;
+  P.iters = iters_out_dev;
+  P.status = status_out_dev;
+  P.f_trace = f_trace_dev;
+  P.x_trace = x_trace_dev;
+  P.err = x->err;
+  if (!s_dev) {   // the context's chains: keep V, the best state and the coordinates current
+    P.v_state = x->v;
+    P.s_best = x->s_best;
+  }
+  const size_t lds = amh::lbfgs_lds_bytes(L, amh::kGradThreads / 64, o->m, o->nonmonotone);
+  if (lds > kMaxLds) return sfail(AMH_E_INVAL, "L=%d needs %zu bytes of LDS for L-BFGS", L, lds);
+  HIP_OK(hipFuncSetAttribute((const void*)amh::lbfgs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL(amh::lbfgs_kernel, dim3(B), dim3(amh::kGradThreads), lds, x->stream, P);
+  HIP_OK(hipGetLastError());
+  if (!s_dev) {
+    amh::ConfParams cp{};
+    cp.L = L;
+    cp.s_in = x->s;
+    cp.atoms64_out = x->atoms;
+    return launch_conf(cp, B, x->stream);
+  }
+  return AMH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* amh_last_error(void) { return g_last_error.c_str(); }
@@ -252,14 +373,19 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   int G = 0, W = 0;
   size_t lds = 0;
   int dev = 0, n_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+  const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+  if (!have_dev || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n_cu < 1)
     n_cu = 256;
   amh_status st = validate(cfg, n_cu, &G, &W, &lds);
   if (st != AMH_OK) return st;
   if (!y_dev) return sfail(AMH_E_INVAL, "distogram table is NULL");
+  if (!have_dev) return sfail(AMH_E_DEVICE, "no current HIP device");
+  double* scratch_dev = nullptr;
+  if ((st = scratch_address(dev, &scratch_dev)) != AMH_OK) return st;
   amh_ctx* x = new amh_ctx;
   x->cfg = *cfg;
+  x->scratch = scratch_dev;
   x->stream = reinterpret_cast<hipStream_t>(stream);
   x->G = G;
   x->W = W;
@@ -534,74 +660,15 @@ amh_status amh_grad(amh_ctx* x, const double* s_dev, int32_t B, double* V_out_de
 amh_status amh_minimize(amh_ctx* x, double* s_dev, int32_t B, const amh_lbfgs_opts* o,
                         double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
                         double* f_trace_dev, double* x_trace_dev) {
-  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
-  if (!o) return sfail(AMH_E_INVAL, "opts is NULL");
-  if (B < 0) return sfail(AMH_E_INVAL, "B < 0");
-  if (!s_dev && B != x->cfg.n_chains)
-    return sfail(AMH_E_INVAL, "B=%d must equal n_chains=%d when s is NULL", B, x->cfg.n_chains);
-  if (o->n_iter < 0) return sfail(AMH_E_INVAL, "n_iter=%d < 0", o->n_iter);
-  if (o->m < 1 || o->m > amh::kLbfgsMaxHistory)
-    return sfail(AMH_E_INVAL, "m=%d outside [1, %d]", o->m, amh::kLbfgsMaxHistory);
-  if (o->nonmonotone < 1 || o->nonmonotone > amh::kLbfgsMaxNonmonotone)
-    return sfail(AMH_E_INVAL, "nonmonotone=%d outside [1, %d]", o->nonmonotone, amh::kLbfgsMaxNonmonotone);
-  if (o->max_ls < 1) return sfail(AMH_E_INVAL, "max_ls=%d < 1", o->max_ls);
-  if (!(o->c1 > 0.0 && o->c1 < 1.0)) return sfail(AMH_E_INVAL, "c1 must lie in (0, 1)");
-  if (!(o->shrink > 0.0 && o->shrink < 1.0)) return sfail(AMH_E_INVAL, "shrink must lie in (0, 1)");
-  if (!(o->gtol >= 0.0) || !std::isfinite(o->gtol)) return sfail(AMH_E_INVAL, "gtol must be finite and >= 0");
-  if (!(o->step0 > 0.0) || !std::isfinite(o->step0)) return sfail(AMH_E_INVAL, "step0 must be finite and > 0");
-  if (B == 0) return AMH_OK;
-  const int L = x->cfg.L;
-  const size_t need = amh::lbfgs_work_doubles(L, o->m) * (size_t)B;
-  if (need > x->work_n) {
-    HIP_OK(hipStreamSynchronize(x->stream));
-    (void)hipFree(x->work);
-    x->work = nullptr;
-    x->work_n = 0;
-    amh_status st = dev_alloc(&x->work, need);
-    if (st != AMH_OK) return st;
-    x->work_n = need;
-  }
-  amh::LbfgsParams P{};
-  P.L = L;
-  P.s = s_dev ? s_dev : x->s;
-  P.table = x->table;
-  P.stride = x->stride;
-  P.nb = x->cfg.n_bins;
-  P.d_min = x->cfg.d_min;
-  P.bin_w = x->cfg.bin_w;
-  P.n_iter = o->n_iter;
-  P.m = o->m;
-  P.nonmonotone = o->nonmonotone;
-  P.max_ls = o->max_ls;
-  P.c1 = o->c1;
-  P.shrink = o->shrink;
-  P.gtol = o->gtol;
-  P.step0 = o->step0;
-  P.work = x->work;
-  P.V = V_out_dev;
-  P.iters = iters_out_dev;
-  P.status = status_out_dev;
-  P.f_trace = f_trace_dev;
-  P.x_trace = x_trace_dev;
-  P.err = x->err;
-  if (!s_dev) {   // the context's chains: keep V, the best state and the coordinates current
-    P.v_state = x->v;
-    P.s_best = x->s_best;
-  }
-  const size_t lds = amh::lbfgs_lds_bytes(L, amh::kGradThreads / 64, o->m, o->nonmonotone);
-  if (lds > kMaxLds) return sfail(AMH_E_INVAL, "L=%d needs %zu bytes of LDS for L-BFGS", L, lds);
-  HIP_OK(hipFuncSetAttribute((const void*)amh::lbfgs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-  hipLaunchKernelGGL(amh::lbfgs_kernel, dim3(B), dim3(amh::kGradThreads), lds, x->stream, P);
-  HIP_OK(hipGetLastError());
-  if (!s_dev) {
-    amh::ConfParams cp{};
-    cp.L = L;
-    cp.s_in = x->s;
-    cp.atoms64_out = x->atoms;
-    return launch_conf(cp, B, x->stream);
-  }
-  return AMH_OK;
+  return minimize_impl(x, s_dev, B, o, V_out_dev, iters_out_dev, status_out_dev, f_trace_dev,
+                       x_trace_dev, false);
+}
+
+amh_status amh_minimize_noalloc(amh_ctx* x, double* s_dev, int32_t B, const amh_lbfgs_opts* o,
+                                double* V_out_dev, int32_t* iters_out_dev, int32_t* status_out_dev,
+                                double* f_trace_dev, double* x_trace_dev) {
+  return minimize_impl(x, s_dev, B, o, V_out_dev, iters_out_dev, status_out_dev, f_trace_dev,
+                       x_trace_dev, true);
 }
 
 amh_status amh_destroy(amh_ctx* x) {

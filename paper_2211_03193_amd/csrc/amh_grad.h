@@ -13,6 +13,10 @@ constexpr unsigned int kErrGradEnergy = kErrEnergy;
 constexpr int kGradThreads = 256;
 constexpr int kLbfgsMaxHistory = 64;
 constexpr int kLbfgsMaxNonmonotone = 64;
+// Fixed L-BFGS workspace of amh_minimize_noalloc: 8 Mi doubles (64 MiB) per device,
+// e.g. 499 conformations of 400 residues with m = 8 (16,800 doubles each).
+constexpr long long kNoallocScratchDoubles = 8LL << 20;
+constexpr int kMaxDevices = 64;
 
 struct GradParams {
   int L;

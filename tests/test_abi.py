@@ -82,6 +82,8 @@ def test_null_arguments_rejected(amh):
     assert amh.lib().amh_grad(None, None, 1, None, None) == amh.E_INVAL
     opts = amh.lbfgs_opts()
     assert amh.lib().amh_minimize(None, None, 1, C.byref(opts), None, None, None, None, None) == amh.E_INVAL
+    assert amh.lib().amh_minimize_noalloc(None, None, 1, C.byref(opts), None, None, None, None,
+                                          None) == amh.E_INVAL
 
 
 def test_lbfgs_opts_layout(amh):
