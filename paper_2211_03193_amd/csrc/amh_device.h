@@ -188,6 +188,28 @@ __device__ __forceinline__ float eval_dev(const Stencil& s) {
   return catmull_rom(s.y0, s.y1, s.y2, s.y3, s.f);
 }
 
+// Branch-free form for several pairs in flight: the address of the stencil of a
+// squared distance in `dev_row`, or of the same taps of the zero row beyond the last
+// knot (d2 = +inf marks an unused slot), and the fraction.  Loads from the returned
+// address can be issued for all slots before any is used.
+__device__ __forceinline__ const float* stencil_addr(const float* __restrict__ dev_row,
+                                                     const float* __restrict__ zrow, float d2,
+                                                     const Spline32& S, float d2far, float& f) {
+  int b;
+  spline_pos(__builtin_amdgcn_sqrtf(fminf(d2, d2far)), S, b, f);
+  return (d2 < d2far ? dev_row : zrow) + b;
+}
+__device__ __forceinline__ float4 ld_stencil(const float* q) {
+  return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+// rint(x 2^30) as a float64 integer: x 2^30 is exact in float32 and rounding it to an
+// integer there equals rounding the exact value, so sums of these integers (below
+// 2^53) are exact in float64 in any order; the energy is the sum times 2^-30.
+__device__ __forceinline__ double fixed30_units(float x) {
+  return (double)rintf(x * 1073741824.0f);
+}
+
 __device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,
                                            double d_min, double w) {
   const double t = (d - (d_min + 0.5 * w)) / w;

@@ -194,15 +194,15 @@ struct Lds {
   __device__ double* red() const { return reinterpret_cast<double*>(par() + 2 * G); }
   __device__ double* red64(int W) const { return red() + 2 * W * G; }
   __device__ double* Vtmp(int W) const { return red64(W) + 2 * W; }
-  // progress of the pipelined localized sweeps: [G][W] ints, then W int64 accept counts
+  // progress of the pipelined localized sweeps: [W] ints, then [W][G] int64 accept counts
   __device__ int* prog(int W) const { return reinterpret_cast<int*>(Vtmp(W) + G); }
   __device__ long long* nacc(int W) const {
-    return reinterpret_cast<long long*>(prog(W) + ((G * W + 1) & ~1));
+    return reinterpret_cast<long long*>(prog(W) + ((W + 1) & ~1));
   }
   // per-wavefront queue of 64 near pairs of a global proposal (row, column, chain, d^2)
   // (offsets from base, not integer addresses, so that the compiler keeps LDS accesses)
   __device__ uint2* qbuf(int W, int wave) const {
-    const size_t o = (size_t)(reinterpret_cast<unsigned char*>(nacc(W) + W) - base);
+    const size_t o = (size_t)(reinterpret_cast<unsigned char*>(nacc(W) + W * G) - base);
     return reinterpret_cast<uint2*>(base + ((o + 15) & ~(size_t)15)) + 64 * wave;
   }
   // bounding spheres (centroid, radius) of the blocks of 8 residues of chain g
@@ -213,7 +213,7 @@ struct Lds {
 
 size_t sweep_lds_bytes(int G, int L, int W) {
   return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
-         8 * (size_t)G + 4 * (size_t)((G * W + 1) & ~1) + 8 * (size_t)W + 64 + 16 +
+         8 * (size_t)G + 4 * (size_t)((W + 1) & ~1) + 8 * (size_t)W * G + 64 + 16 +
          8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8);
 }
 
@@ -278,7 +278,12 @@ __device__ __forceinline__ void trace_step(const SweepParams& P, int slot, int64
   P.tr_acc[slot * P.trace_cap + idx] = (uint8_t)acc;
 }
 
-// Localized sweep of chain g by its owner wavefront (no workgroup barrier inside).
+// Localized sweeps run all chains of a workgroup side by side in one wavefront:
+// chain q owns the LW = 64 / G lanes [q LW, (q + 1) LW), and every chain is at the
+// same proposal k of the same sweep, so the window bounds are uniform and only the
+// geometry differs between the lane groups.  The wavefronts of a workgroup are
+// consecutive sweeps of a block, pipelined.
+//
 // Pipelining: the m-th sweep of a block of consecutive localized sweeps publishes
 // m * 4096 + (proposals done) in `publish`; sweep m+1 waits on that counter so that
 // it runs proposal k' (residue c') only once sweep m stands at residue c'+2h+1 or
@@ -291,123 +296,193 @@ struct Pipe {
   int m;                // index of the sweep in its block
 };
 
-__device__ __forceinline__ bool wait_progress(const SweepParams& P, const int* ctr, int target,
-                                              bool& stalled) {
-  if (stalled) return false;
+// Waits until *ctr >= target and returns the value seen (bounded: on a stall the
+// error word is flagged and the sweep goes on rather than hang).
+__device__ __forceinline__ int wait_progress(const SweepParams& P, const int* ctr, int target,
+                                             bool& stalled) {
+  if (stalled) return 0x7fffffff;
   for (int spin = 0; spin < P.spin_limit; ++spin) {
-    if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
+    const int v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (v >= target) return v;
     __builtin_amdgcn_s_sleep(2);
   }
-  stalled = true;   // bounded wait: flag the error and go on rather than hang
+  stalled = true;
   atomicOr(P.err, kErrStall);
-  return false;
+  return 0x7fffffff;
 }
 
-__device__ void local_sweep(const SweepParams& P, const Lds& S, int g, int chain, int64_t t,
+// Value of lane (q LW + kl) for the lanes of chain group q (kl uniform).
+template <int LW>
+__device__ __forceinline__ double group_bcast(double v, int lane, int kl) {
+  if constexpr (LW == 64) {
+    return readlane_d(v, kl);
+  } else {
+    const int src = ((lane & ~(LW - 1)) + kl) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+  }
+}
+
+// Sum over the LW lanes of each chain group; every lane of a group gets its group's
+// sum.  The addends are multiples of 2^-30 below 2^23 in magnitude, so every partial
+// sum is exact and the result does not depend on LW or on the order.
+template <int LW>
+__device__ __forceinline__ double group_sum(double v, int lane) {
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppRor4>(v);
+  v += dpp_d<kDppRor8>(v);   // every lane: the sum of its row of 16
+  if constexpr (LW == 16) {
+    return v;
+  } else if constexpr (LW == 32) {
+    const double a = readlane_d(v, 0) + readlane_d(v, 16), b = readlane_d(v, 32) + readlane_d(v, 48);
+    return lane < 32 ? a : b;
+  } else {
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  }
+}
+
+// A pair's deviation energy rounded to a multiple of 2^-30: sums of such terms
+// (|sum| < 2^23) are exact in float64 whatever the order of the additions, so every
+// launch shape, batch and lane assignment gives the same value (the rounding,
+// < 1e-9 per pair, is far inside the parity tolerance).
+__device__ __forceinline__ double fixed30(float x) {
+  return rint((double)x * 1073741824.0) * (1.0 / 1073741824.0);
+}
+
+// One localized sweep of the workgroup's chains (G of them, nact active) by one
+// wavefront, with no workgroup barrier inside.
+template <int G>
+__device__ void local_sweep(const SweepParams& P, const Lds& S, int nact, int c0, int64_t t,
                             double beta, int h, int h_prev, int lane, int slot, int64_t& n_acc,
                             const Pipe& pipe, bool& stalled) {
+  constexpr int LW = 64 / G;   // lanes per chain
+  constexpr int R = G > 2 ? 3 : G;   // pair slots per lane: LW R pairs per pass (48 at G = 4)
   const int L = P.L, n = 2 * L;
-  double* __restrict__ x64 = S.x64(g);
-  double* __restrict__ s = S.s(g);
+  const int q = lane / LW, ll = lane - q * LW;
+  const bool act = q < nact;
+  double* __restrict__ x64 = S.x64(q);
+  double* __restrict__ s = S.s(q);
+  const uint32_t chain = (uint32_t)(P.chain_offset + c0 + q);
   const Spline32 sp{P.inv_w, P.off, P.tmax};
   // accumulated rigid transform x -> A x + b of the residues that have not yet
-  // entered the window (float64, uniform over the wave)
+  // entered the window (float64, uniform over the chain's lanes)
   double A[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, tb[3] = {0, 0, 0};
   bool moved = false;
   int entered = h < L - 1 ? h : L - 1;
+  int seen = -1;   // progress of the previous sweep last read
   Batch bt{};
   for (int k = 0; k < n; ++k) {
-    if ((k & 63) == 0) bt = fill_batch(P, k, (uint32_t)t, (uint32_t)(P.chain_offset + chain), lane);
+    const int kl = k & (LW - 1);
+    if (kl == 0) bt = fill_batch(P, k, (uint32_t)t, chain, ll);
+    // this proposal's randoms from the lane of the chain that drew them
+    const double cd = group_bcast<LW>(bt.cd, lane, kl), sd = group_bcast<LW>(bt.sd, lane, kl);
+    const double log_u = group_bcast<LW>(bt.log_u, lane, kl), delta = group_bcast<LW>(bt.delta, lane, kl);
     const int c = k >> 1, p = (k & 1) ? c + 1 : c;
     const int lo = c - h > 0 ? c - h : 0, hi = c + h < L - 1 ? c + h : L - 1;
     if (pipe.wait_on) {
       // the previous sweep (half-width h_prev) must be done with every proposal whose
       // window reaches residue c + h, i.e. with all proposals up to c' = c + h + h_prev
-      const int need = 2 * (c + h + h_prev) + 2 < n ? 2 * (c + h + h_prev) + 2 : n;
-      wait_progress(P, pipe.wait_on, (pipe.m - 1) * 4096 + need, stalled);
+      const int need = (pipe.m - 1) * 4096 +
+                       (2 * (c + h + h_prev) + 2 < n ? 2 * (c + h + h_prev) + 2 : n);
+      if (seen < need) seen = wait_progress(P, pipe.wait_on, need, stalled);
     }
     // residues entering the window take the transform accumulated so far
     while (entered < hi) {
       ++entered;
-      if (moved && lane < 4) {
-        double* q = atom(x64, entered, lane);
-        const double X = q[0], Y = q[1], Z = q[2];
-        q[0] = A[0] * X + A[1] * Y + A[2] * Z + tb[0];
-        q[1] = A[3] * X + A[4] * Y + A[5] * Z + tb[1];
-        q[2] = A[6] * X + A[7] * Y + A[8] * Z + tb[2];
+      if (moved && ll < 4) {
+        double* qa = atom(x64, entered, ll);
+        const double X = qa[0], Y = qa[1], Z = qa[2];
+        qa[0] = A[0] * X + A[1] * Y + A[2] * Z + tb[0];
+        qa[1] = A[3] * X + A[4] * Y + A[5] * Z + tb[1];
+        qa[2] = A[6] * X + A[7] * Y + A[8] * Z + tb[2];
       }
       wave_sync();
     }
-    const int kl = k & 63;
-    const double delta = readlane_d(bt.delta, kl), log_u = readlane_d(bt.log_u, kl);
     const bool live = k != 0 && k != n - 1;
     const int nF = p - lo > 0 ? p - lo : 0, nM = hi - p + 1 > 0 ? hi - p + 1 : 0;
-    const int npair = nF * nM;
-    double dE = 0.0;
-    Rot R;
-    // the first 64 changed pairs, one per lane: the stencil of the current distance is
-    // fetched before the rotation is set up, so that the two overlap
-    const bool mine = live && lane < npair;
-    D3 xi{0, 0, 0}, xj{0, 0, 0};
-    const float* row = P.ydev;
-    Stencil s0{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (mine) {
-      // lane = a nM + b; the float quotient is exact for lane < 64 (the fraction stays
-      // at least 0.5 / nM away from an integer)
-      const int a = (int)(((float)lane + 0.5f) / (float)nM), ii = lo + a, j = p + (lane - a * nM);
-      xi = ld3(atom(x64, ii, 3));
-      xj = ld3(atom(x64, j, 3));
-      row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
-      s0 = fetch_dev(row, dist2_64(xi, xj), sp, P.d2far);
-    }
-    if (live) {
-      D3 a, b;
-      axis_atoms(x64, k, a, b);
-      make_rot(a, b, readlane_d(bt.cd, kl), readlane_d(bt.sd, kl), R);
-      if (npair > 0) {
-        double part = 0.0;
-        if (mine) {
-          const float e1 = edev32(row, dist2_64(xi, apply_rot(R, xj)), sp, P.d2far);
-          part = (double)e1 - (double)eval_dev(s0);
-        }
-        for (int x = lane + 64; x < npair; x += 64) {   // windows wider than 64 pairs
-          const int ii = lo + x / nM, j = p + x % nM;
-          const D3 yi = ld3(atom(x64, ii, 3)), yj = ld3(atom(x64, j, 3));
-          const float* r2 = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
-          const float e0 = edev32(r2, dist2_64(yi, yj), sp, P.d2far);
-          const float e1 = edev32(r2, dist2_64(yi, apply_rot(R, yj)), sp, P.d2far);
-          part += (double)e1 - (double)e0;
-        }
-        dE = wave_sum_dpp(part);
+    const int npair = live ? nF * nM : 0;
+    const float inv_nM = 1.0f / (float)(nM > 0 ? nM : 1);
+    double part = 0.0;
+    Rot Rk;
+    // the changed pairs (lo + a, p + b), a in [0, nF), b in [0, nM), in passes of LW R:
+    // pair x = a nM + b sits in slot (x mod LW R) / LW of lane x mod LW.  The stencils
+    // of the current distances are fetched before the rotation is set up; only the
+    // stencils stay in registers, the coordinates are read again afterwards
+    for (int x0 = 0; x0 < npair || x0 == 0; x0 += LW * R) {
+      // branch-free over the slots, so that all their loads are in flight together:
+      // an unused slot reads atoms of the window and the zero row
+      int pr[R];   // (row residue << 16) | column residue of the slot's pair
+      float4 q0[R];
+      float f0[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = x0 + r * LW + ll;
+        // floor((x + 1/2) / nM) is exact through the float reciprocal for x < 2^22
+        const int a = (int)(((float)x + 0.5f) * inv_nM);
+        const bool use = x < npair;
+        const int ii = use ? lo + a : lo, j = use ? p + (x - a * nM) : p;
+        pr[r] = (ii << 16) | j;
+        const float d2 = use ? dist2_64(ld3(atom(x64, ii, 3)), ld3(atom(x64, j, 3))) : __builtin_inff();
+        const float* row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
+        q0[r] = ld_stencil(stencil_addr(row, P.zrow, d2, sp, P.d2far, f0[r]));
       }
+      if (x0 == 0 && live) {
+        D3 a, b;
+        axis_atoms(x64, k, a, b);
+        make_rot(a, b, cd, sd, Rk);
+      }
+      float4 q1[R];
+      float f1[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int ii = pr[r] >> 16, j = pr[r] & 0xffff;
+        const float d2 = x0 + r * LW + ll < npair
+                             ? dist2_64(ld3(atom(x64, ii, 3)), apply_rot(Rk, ld3(atom(x64, j, 3))))
+                             : __builtin_inff();
+        const float* row = P.ydev + (size_t)pair_row(ii, j, L) * P.stride;
+        q1[r] = ld_stencil(stencil_addr(row, P.zrow, d2, sp, P.d2far, f1[r]));
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        part += fixed30_units(catmull_rom(q1[r].x, q1[r].y, q1[r].z, q1[r].w, f1[r])) -
+                fixed30_units(catmull_rom(q0[r].x, q0[r].y, q0[r].z, q0[r].w, f0[r]));
     }
+    const double dE = npair > 0 ? group_sum<LW>(act ? part : 0.0, lane) * (1.0 / 1073741824.0) : 0.0;
     const int acc = (dE <= 0.0) || (log_u < -beta * dE);
-    if (lane == 0 && !isfinite(dE)) atomicOr(P.err, kErrEnergy);
-    trace_step(P, lane == 0 ? slot : -1, t, k, dE, delta, acc);
-    if (acc) {
-      if (lane == 0) s[k] = wrap_angle(s[k] + delta);
+    if (act && ll == 0 && !isfinite(dE)) atomicOr(P.err, kErrEnergy);
+    trace_step(P, act && ll == 0 ? slot : -1, t, k, dE, delta, acc);
+    if (act && acc) {
+      if (ll == 0) s[k] = wrap_angle(s[k] + delta);
       ++n_acc;
       if (live) {
-        // rotate the atoms of the entered residues p..entered that the torsion moves
-        const int nres = entered - p + 1;
-        for (int x = lane; x < 4 * nres; x += 64) {
-          const int r = p + (x >> 2), at = x & 3;
-          if (!(k & 1) && r == c && at < 2) continue;   // phi_c leaves N_c and CA_c in place
-          double* q = atom(x64, r, at);
-          st3(q, apply_rot(R, ld3(q)));
+        // rotate the atoms of the entered residues p..entered that the torsion moves,
+        // two per lane at a time (both read before either is written)
+        const int nat = 4 * (entered - p + 1);
+        for (int x0 = 0; x0 < nat; x0 += 2 * LW) {
+          const int xa = x0 + ll, xb = xa + LW;
+          const int ya = xa < nat ? xa : nat - 1, yb = xb < nat ? xb : nat - 1;
+          // phi_c leaves N_c and CA_c in place
+          const bool va = xa < nat && ((k & 1) || xa >= 2), vb = xb < nat && ((k & 1) || xb >= 2);
+          double* qa = atom(x64, p + (ya >> 2), ya & 3);
+          double* qb = atom(x64, p + (yb >> 2), yb & 3);
+          const D3 ra = apply_rot(Rk, ld3(qa)), rb = apply_rot(Rk, ld3(qb));
+          if (va) st3(qa, ra);
+          if (vb) st3(qb, rb);
         }
         // compose the pending transform: x -> R (x - a) + a after (A, b)
         double nA[9], nb[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
 #pragma unroll
-          for (int q = 0; q < 3; ++q)
-            nA[3 * r + q] = R.r[3 * r] * A[q] + R.r[3 * r + 1] * A[3 + q] + R.r[3 * r + 2] * A[6 + q];
-          nb[r] = R.r[3 * r] * (tb[0] - R.a[0]) + R.r[3 * r + 1] * (tb[1] - R.a[1]) +
-                  R.r[3 * r + 2] * (tb[2] - R.a[2]) + R.a[r];
+          for (int qq = 0; qq < 3; ++qq)
+            nA[3 * r + qq] = Rk.r[3 * r] * A[qq] + Rk.r[3 * r + 1] * A[3 + qq] + Rk.r[3 * r + 2] * A[6 + qq];
+          nb[r] = Rk.r[3 * r] * (tb[0] - Rk.a[0]) + Rk.r[3 * r + 1] * (tb[1] - Rk.a[1]) +
+                  Rk.r[3 * r + 2] * (tb[2] - Rk.a[2]) + Rk.a[r];
         }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) A[q] = nA[q];
+        for (int qq = 0; qq < 9; ++qq) A[qq] = nA[qq];
         tb[0] = nb[0]; tb[1] = nb[1]; tb[2] = nb[2];
         moved = true;
       }
@@ -453,14 +528,6 @@ __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int
   __syncthreads();
 }
 
-// A pair's deviation energy rounded to a multiple of 2^-30: the rectangle sums of
-// a global sweep (|sum| < 2^23) are then exact in float64 whatever the order of
-// the additions, so every launch shape, batch and lane assignment carries the same
-// value (the rounding, < 1e-9 per pair, is far inside the parity tolerance).
-__device__ __forceinline__ double fixed30(float x) {
-  return rint((double)x * 1073741824.0) * (1.0 / 1073741824.0);
-}
-
 // acc[g] += v for a lane-varying chain index g (kept in registers).
 template <int G>
 __device__ __forceinline__ void add_chain(double* acc, int g, double v) {
@@ -490,6 +557,12 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
     const int g = e / n, m = e % n;
     S.s(g)[m] = P.s[(size_t)(c0 + g) * n + m];
   }
+  // the slots of absent chains (a last workgroup with nact < G) hold zeros: their
+  // lanes of the localized sweeps compute on them without any effect
+  for (int e = tid; e < (G - nact) * L * 12; e += T) {
+    const int g = nact + e / (12 * L);
+    S.x64(g)[e - (g - nact) * 12 * L] = 0.0;
+  }
   // per-chain registers of the owner wavefront
   int64_t acc_local = 0, acc_global = 0, ttt = -1, nanchor = 0;
   const bool owner = wave < nact;
@@ -504,12 +577,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
   }
   __syncthreads();
 
-  // the W/G wavefronts of chain g (waves g, g+G, ...) run the consecutive localized
-  // sweeps of a block in turn, pipelined
-  const int nstage = W / G, stage = wave / G, lg = wave - stage * G;
-  const bool stage_wave = stage < nstage && lg < nact;
-  const int lslot = stage_wave ? trace_slot(P, c0 + lg) : -1;
-  int64_t acc_local_stage = 0;
+  // every wavefront runs all chains of the workgroup (LW lanes each); the W wavefronts
+  // run the consecutive localized sweeps of a block in turn, pipelined
+  const int nstage = W, stage = wave;
+  const int lslot = (lane / (64 / G)) < nact ? trace_slot(P, c0 + lane / (64 / G)) : -1;
+  int64_t acc_local_stage = 0;   // accepted localized proposals of this lane's chain
   bool stalled = false;
   const int64_t t_end = P.t0 + P.n_sweeps;
   for (int64_t t = P.t0; t < t_end;) {
@@ -527,21 +599,19 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         if ((tb % P.anchor_every) == 0) break;
       }
       const int nblk = (int)(tb - t);
-      for (int e = tid; e < G * W; e += T) S.prog(W)[e] = 0;
+      for (int e = tid; e < W; e += T) S.prog(W)[e] = 0;
       __syncthreads();
-      if (stage_wave) {
-        for (int m = stage; m < nblk; m += nstage) {
-          const int64_t tm = t + m;
-          double Tm = P.T0;
-          if (P.S > 1) Tm = P.T0 * pow(P.T1 / P.T0, (double)tm / (double)(P.S - 1));
-          Pipe pipe;
-          pipe.m = m;
-          pipe.publish = S.prog(W) + lg * W + stage;
-          pipe.wait_on = m > 0 ? S.prog(W) + lg * W + ((m - 1) % nstage) : nullptr;
-          local_sweep(P, S, lg, c0 + lg, tm, 1.0 / Tm, half_window_at(P, tm),
-                      tm > 0 ? half_window_at(P, tm - 1) : 0, lane, lslot, acc_local_stage, pipe,
-                      stalled);
-        }
+      for (int m = stage; m < nblk; m += nstage) {
+        const int64_t tm = t + m;
+        double Tm = P.T0;
+        if (P.S > 1) Tm = P.T0 * pow(P.T1 / P.T0, (double)tm / (double)(P.S - 1));
+        Pipe pipe;
+        pipe.m = m;
+        pipe.publish = S.prog(W) + stage;
+        pipe.wait_on = m > 0 ? S.prog(W) + ((m - 1) % nstage) : nullptr;
+        local_sweep<G>(P, S, nact, c0, tm, 1.0 / Tm, half_window_at(P, tm),
+                       tm > 0 ? half_window_at(P, tm - 1) : 0, lane, lslot, acc_local_stage, pipe,
+                       stalled);
       }
       __syncthreads();
       t = tb;
@@ -700,14 +770,15 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         for (int g = 0; g < G; ++g) {
           if (g < nact) {
             const double a = wave_sum_dpp(acc[g]), b = wave_sum_dpp(tr[g]);
-            if (lane == 0) { S.red()[(2 * g) * W + wave] = a; S.red()[(2 * g + 1) * W + wave] = b; }
+            // wave-major partials: one base address per wavefront, constant offsets
+            if (lane == 0) { S.red()[wave * 2 * G + 2 * g] = a; S.red()[wave * 2 * G + 2 * g + 1] = b; }
           }
         }
         __syncthreads();
         // [D] every wavefront takes the same decisions from the same partials: lane
         // l < 2 W G holds partial (wave v, chain g, kind c) and the W waves of each
         // (g, c) are summed in a fixed order
-        double part = lane < 2 * W * G ? S.red()[lane] : 0.0;
+        double part = lane < 2 * W * G ? S.red()[(lane % W) * 2 * G + lane / W] : 0.0;
         // sum each aligned group of W lanes: quad sums by DPP butterflies, then the
         // quads of a group in lane order (W = 4 or 8; other W lane by lane)
         if (W == 4 || W == 8) {
@@ -806,11 +877,10 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
 
   // store chain state; the localized-sweep accept counts of a chain's waves are summed
   __syncthreads();
-  if (lane == 0) S.nacc(W)[wave] = acc_local_stage;
+  if ((lane & (64 / G - 1)) == 0) S.nacc(W)[wave * G + lane / (64 / G)] = acc_local_stage;
   __syncthreads();
   if (owner)
-    for (int q = 1; q < nstage; ++q) acc_local_stage += S.nacc(W)[wave + q * G];
-  acc_local += acc_local_stage;
+    for (int v = 0; v < W; ++v) acc_local += S.nacc(W)[v * G + wave];
   for (int e = tid; e < nact * L * 12; e += T) {
     const int g = e / (12 * L), q = e - g * 12 * L;
     P.atoms[(size_t)(c0 + g) * L * 12 + q] = S.x64(g)[q];
