@@ -628,6 +628,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       // blocks of 8 residues for the rectangle's tiles; a tile is skipped when its
       // spheres are more than rcut apart (the last knot + 0.05 A)
       const int nb8 = (L + 7) >> 3, nres8 = 8 * nb8;
+      const float inv_nres8 = 1.0f / (float)nres8;
       const float rcut = __builtin_amdgcn_sqrtf(P.d2far) + 0.05f;
       if (owner) {
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
@@ -647,7 +648,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         // bounding sphere (centroid, radius) of every block of 8 consecutive residues;
         // the 8 residues of a block sit in 8 aligned lanes of one wavefront
         for (int e0 = 0; e0 < nact * nres8; e0 += T) {
-          const int e = e0 + tid, g = e / nres8, r = e - g * nres8;
+          // floor((e + 1/2) / nres8) through the float reciprocal (exact for e < 2^22)
+          const int e = e0 + tid, g = (int)(((float)e + 0.5f) * inv_nres8), r = e - g * nres8;
           const bool real = g < nact && r < L;
           float vx = 0.0f, vy = 0.0f, vz = 0.0f;
           if (real) {
@@ -759,17 +761,24 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
             if (x < p - 1) { i = x; j = p - 1; sgn = -1.0; }
             else { i = p - 1; j = p + (x - (p - 1)); sgn = 1.0; }
             const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
+            // the G chains' stencils are loaded together (absent chains read the zero row)
+            float4 qv[G];
+            float fv[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const float d2 = g < nact ? dist2_64(ld3(atom(S.x64(g), i, 3)), ld3(atom(S.x64(g), j, 3)))
+                                        : __builtin_inff();
+              qv[g] = ld_stencil(stencil_addr(row, P.zrow, d2, sp, P.d2far, fv[g]));
+            }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-              if (g < nact)
-                tr[g] += sgn * fixed30(edev32(row, dist2_64(ld3(atom(S.x64(g), i, 3)),
-                                                            ld3(atom(S.x64(g), j, 3))), sp, P.d2far));
+              tr[g] += sgn * fixed30(catmull_rom(qv[g].x, qv[g].y, qv[g].z, qv[g].w, fv[g]));
           }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           if (g < nact) {
-            const double a = wave_sum_dpp(acc[g]), b = wave_sum_dpp(tr[g]);
+            const double a = wave_sum_dpp(acc[g]), b = (k & 1) ? wave_sum_dpp(tr[g]) : 0.0;
             // wave-major partials: one base address per wavefront, constant offsets
             if (lane == 0) { S.red()[wave * 2 * G + 2 * g] = a; S.red()[wave * 2 * G + 2 * g + 1] = b; }
           }
@@ -842,8 +851,9 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         // [E] commit accepted moves: rotate (float64) every atom the torsion moves
         if (accmask) {
           const int per = 4 * M;
+          const float inv_per = 1.0f / (float)per;
           for (int e = tid; e < nact * per; e += T) {
-            const int g = e / per;
+            const int g = (int)(((float)e + 0.5f) * inv_per);   // e / per, exact for e < 2^22
             if (!((accmask >> g) & 1)) continue;
             const int x = e - g * per, r = p + (x >> 2), at = x & 3;
             if (!(k & 1) && r == c && at < 2) continue;   // phi_c leaves N_c and CA_c in place
