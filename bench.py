@@ -24,7 +24,13 @@ import numpy as np  # noqa: E402
 import synthetic as sy  # noqa: E402
 
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9    # FLOP/s: 256 CUs x 64 lanes x FMA x 2.4 GHz
+PEAK_FP32_PUBLISHED = 157.3e12                 # FLOP/s, MI355X vector FP32 (packed)
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_L300_1024chains_traffic.json")
+# algorithmic operation counts of the executed work of a sweep launch (FP32-equivalent):
+FLOPS_TEST = 9.0      # squared distance of a float32 pair and its comparison with the last knot
+FLOPS_SPLINE = 20.0   # square root, knot interval and fraction, Catmull-Rom cubic of one stencil
+FLOPS_ROTATE = 18.0   # float64 rotation of one moved C-beta about the bond and the difference
+STENCIL_BYTES = 16    # one 4-tap float32 stencil gathered from the distogram table
 
 
 def code_digest(paths) -> str:
@@ -77,7 +83,40 @@ def pair_evals_per_cycle(L: int, d: int, cycle: int) -> tuple[int, int]:
     return glob, loc * (cycle - 1)
 
 
-def gpu_leg(w, steps, warmup, G=0, W=0):
+def schedule_work(L: int, d: int, cycle: int) -> dict:
+    """Work of one chain in one alternation cycle that the schedule fixes (no
+    counting needed): localized changed pairs (two stencils each), candidate tiles
+    of the global rectangle (8 x 8 residue blocks), transition pairs of the psi
+    proposals and the anchor's pairs."""
+    nb8 = (L + 7) // 8
+    cand = 0
+    for k in range(2 * L):
+        p = (k + 1) // 2
+        if p >= 1 and L - p >= 1:
+            cand += (((p - 1) >> 3) + 1) * (nb8 - (p >> 3))
+    _, loc = pair_evals_per_cycle(L, d, cycle)
+    return {"local_pairs": loc, "candidate_tiles": cand, "transition_pairs": L * (L - 1),
+            "anchor_pairs": L * (L - 1) // 2}
+
+
+def executed_work(fixed: dict, counted: dict, chains: int) -> dict:
+    """Per-launch executed work: the schedule's part times the chains, plus the
+    counted global-sweep part (surviving tiles, pair tests, near pairs)."""
+    loc = fixed["local_pairs"] * chains
+    trans = fixed["transition_pairs"] * chains
+    anch = fixed["anchor_pairs"] * chains
+    tests = counted["pair_tests"]
+    near = counted["near_pairs"]
+    stencils = 2 * loc + near + trans + anch
+    flops = (FLOPS_TEST * (tests + fixed["candidate_tiles"] * chains + 2 * loc + trans + anch)
+             + FLOPS_SPLINE * stencils + FLOPS_ROTATE * loc)
+    return {"local_pairs": loc, "candidate_tiles": fixed["candidate_tiles"] * chains,
+            "surviving_tiles": counted["tiles"], "pair_tests": tests, "near_pairs": near,
+            "transition_pairs": trans, "anchor_pairs": anch, "stencils": stencils,
+            "stencil_bytes": STENCIL_BYTES * stencils, "flops": flops}
+
+
+def gpu_leg(w, steps, warmup, G=0, W=0, target=None, count_work=True):
     import torch
     from paper_2211_03193_amd import amh
 
@@ -89,14 +128,21 @@ def gpu_leg(w, steps, warmup, G=0, W=0):
     yt = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float32)).to(dev)
     ctx = amh.Context(amh.make_config(w, chains_per_group=G, waves_per_group=W), yt)
     V_ref = ctx.energy(torch.from_numpy(s_ref[None]).to(dev))[0].item()
-    target = 1.05 * V_ref
-    ctx.set_target(target)
+    # the device records, per chain, the first anchor sweep at or below the target
+    target_ref = 1.05 * V_ref
+    ctx.set_target(target if target is not None else target_ref)
     info = ctx.info()
     cyc = w.global_every
-    for _ in range(warmup):
-        ctx.sweep(cyc)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    wev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(warmup)]
+    for e0, e1 in wev:
+        e0.record(stream)
+        ctx.sweep(cyc)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    work = torch.zeros(3, dtype=torch.int64, device=dev)
+    if count_work:
+        ctx.set_work_counters(work)
     # per-launch events: one amh_sweep call per step
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
@@ -107,14 +153,18 @@ def gpu_leg(w, steps, warmup, G=0, W=0):
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.set_work_counters(None)
     launch_ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    warm_ms = np.array([e0.elapsed_time(e1) for e0, e1 in wev])
     ctx.poll()
     st = ctx.get_state()
     v = st["v"].cpu().numpy()
     cnt = st["counters"].cpu().numpy()
     ctx.close()
-    return dict(wall=wall, launch_ms=launch_ms, info=info, V_ref=V_ref, target=target,
-                v=v, counters=cnt)
+    wk = work.cpu().numpy()
+    return dict(wall=wall, launch_ms=launch_ms, warm_ms=warm_ms, info=info, V_ref=V_ref,
+                target=target, target_ref=target_ref, v=v, counters=cnt,
+                counted={"tiles": int(wk[0]), "pair_tests": int(wk[1]), "near_pairs": int(wk[2])})
 
 
 def batch_leg(steps, warmup, n_proteins, tune_sweeps):
@@ -414,23 +464,47 @@ def tts_leg(cpu_runs, chains):
     }
 
 
-def cpu_leg(w, cores, sweeps):
+def cpu_leg(w, cores, sweeps, one_core_sweeps=200, target_runs=10, target_proposals=100000):
+    """The float64 oracle on the host: (a) all `cores` threads, two chains each, for
+    `sweeps` sweeps of the workload from the extended chain; (b) one thread, two
+    chains, `one_core_sweeps` sweeps; (c) the paper's time-to-solution target (Sec. 3,
+    Fig. 4E): `target_runs` runs of `target_proposals` proposals each (the workload's
+    schedule compressed to that many sweeps), whose mean lowest energy is the target
+    the device chains must reach."""
     import oracle
+    from oracle import build as obuild
     s_ref = sy.reference_torsions(w.L, w.protein_seed)
     y = sy.distogram(sy.pair_distances(oracle.cb(s_ref)), w.eps, w.noise_seed)
     y32 = np.asarray(y, dtype=np.float32).astype(np.float64)
     cfg = oracle.make_cfg(w)
-    n_chains = 2 * cores
-    ch = oracle.Chains(cfg, y32, np.full((n_chains, 2 * w.L), math.pi),
-                       chain_ids=np.arange(n_chains, dtype=np.uint32))
+
+    def rate(n_chains, n_sweeps, threads):
+        ch = oracle.Chains(cfg, y32, np.full((n_chains, 2 * w.L), math.pi),
+                           chain_ids=np.arange(n_chains, dtype=np.uint32))
+        t0 = time.perf_counter()
+        ch.run(n_sweeps, mode=1, threads=threads)
+        return n_chains * n_sweeps * 2 * w.L / (time.perf_counter() - t0), time.perf_counter() - t0
+
+    flags = " ".join(obuild.FLAGS)
+    v_all, t_all = rate(2 * cores, sweeps, cores)
+    v_one, t_one = rate(2, one_core_sweeps, 1)
+    S = -(-target_proposals // (2 * w.L))
+    wt = w.replace(total_sweeps=S)
+    ch = oracle.Chains(oracle.make_cfg(wt), y32, np.full((target_runs, 2 * w.L), math.pi),
+                       chain_ids=np.arange(target_runs, dtype=np.uint32))
     t0 = time.perf_counter()
-    ch.run(sweeps, mode=1, threads=cores)
-    dt = time.perf_counter() - t0
-    props = n_chains * sweeps * 2 * w.L
-    return dict(value=props / dt, unit="proposals/s", cores=cores, kind="oracle",
-                sample=f"{n_chains} chains x {sweeps} sweeps ({sweeps // w.global_every} "
-                       f"alternation cycles) of the same workload from the extended chain, "
-                       f"incremental FP64 oracle, OpenMP over chains; {dt:.1f} s wall")
+    ch.run(S, mode=1, threads=min(cores, target_runs))
+    t_target = time.perf_counter() - t0
+    lows = [float(x) for x in ch.v[:, 1]]
+    return dict(value=v_all, unit="proposals/s", cores=cores, kind="oracle",
+                sample=f"{2 * cores} chains x {sweeps} sweeps ({sweeps // w.global_every} alternation "
+                       f"cycles) of the same workload from the extended chain, incremental FP64 "
+                       f"oracle, OpenMP over chains; {t_all:.1f} s wall; gcc {flags}",
+                one_core={"value": v_one, "unit": "proposals/s", "cores": 1,
+                          "sample": f"2 chains x {one_core_sweeps} sweeps, one thread; {t_one:.1f} s wall"},
+                target_runs={"runs": target_runs, "proposals_per_run": S * 2 * w.L, "sweeps": S,
+                             "lowest_energies": lows, "mean_lowest": float(np.mean(lows)),
+                             "seconds_per_run_one_core": t_target * min(cores, target_runs) / target_runs})
 
 
 def main():
@@ -446,6 +520,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=800,
                     help="sweeps of the oracle CPU-baseline sample (2 chains per core)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
+    ap.add_argument("--no-yardsticks", action="store_true",
+                    help="skip the achievable-bandwidth yardsticks of the roofline")
     ap.add_argument("--workload", choices=["single", "batch", "serve", "variants", "tts"],
                     default="single",
                     help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
@@ -496,20 +572,33 @@ def main():
     if (args.warmup + args.steps) * cyc > w.total_sweeps:
         sys.exit(f"warmup + steps must fit the {w.total_sweeps}-sweep schedule "
                  f"({w.total_sweeps // cyc} steps)")
-    r = gpu_leg(w, args.steps, args.warmup, args.chains_per_group, args.waves_per_group)
+    cpu = None
+    if rank == 0 and not args.no_cpu:
+        cpu = cpu_leg(w, host_cores(), args.cpu_sweeps)
+    target = cpu["target_runs"]["mean_lowest"] if cpu else None
+    yard = None
+    if not args.no_yardsticks:
+        from paper_2211_03193_amd import amh as _amh
+        yard = _amh.yardsticks()
+    r = gpu_leg(w, args.steps, args.warmup, args.chains_per_group, args.waves_per_group, target=target)
     props_step = w.n_chains * cyc * 2 * w.L
     ms_step = r["wall"] * 1e3 / args.steps
     value = props_step * args.steps / r["wall"]
     glob, loc = pair_evals_per_cycle(w.L, w.window_d, cyc)
-    pairs_step = (glob + loc) * w.n_chains
-    # roofline of the sweep kernel: algorithmic FP32 flops of the pair evaluations per
-    # launch (one launch = one step) over its measured average duration
-    flops_pair = 9.0      # 3 sub + 3 mul/fma (squared distance) + compare -> 9 flops per pair
+    dense_pairs = (glob + loc) * w.n_chains
+    # roofline of the sweep kernel on the work it executes per launch (one launch = one
+    # step): the schedule's fixed part plus the counted global-sweep part, averaged
+    # over the timed launches, over the measured average launch duration
     launch_s = float(np.mean(r["launch_ms"])) * 1e-3
-    achieved = flops_pair * pairs_step / launch_s
+    per_launch = {k: v / args.steps for k, v in r["counted"].items()}
+    ex = executed_work(schedule_work(w.L, w.window_d, cyc), per_launch, w.n_chains)
+    achieved = ex["flops"] / launch_s
+    gather = ex["stencil_bytes"] / launch_s
     cnt = r["counters"]
     ttt = cnt[:, 2]
     reached = ttt[ttt >= 0]
+    all_ms = np.concatenate([r["warm_ms"], r["launch_ms"]])
+    first = int(reached.min()) if reached.size else None
     out = {
         "metric": "proposals/s", "value": value, "unit": "proposals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -521,21 +610,41 @@ def main():
                    "seed": hex(w.seed), "protein_seed": w.protein_seed,
                    "noise_seed": w.noise_seed, "eps": w.eps, "accum_dtype": "f64",
                    "coord_dtype": "f64", "launch": r["info"]},
-        "pair_evals_per_s": pairs_step * args.steps / r["wall"],
+        "pair_evals_per_s": dense_pairs * args.steps / r["wall"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED,
                      "traffic": measured_traffic() if w.name == sy.CFG2.name else None,
                      "traffic_unit": "bytes per launch (HBM)",
                      "kernel": f"sweep_kernel<{r['info']['chains_per_group']}>",
                      "avg_launch_ms": launch_s * 1e3,
-                     "flops_per_pair": flops_pair, "pairs_per_launch": pairs_step},
-        "energy": {"V_ref": r["V_ref"], "target": r["target"],
+                     "work": "executed per launch (fixed by the schedule, plus counted in the kernel)",
+                     "executed_per_launch": ex,
+                     "flops_per": {"pair_test": FLOPS_TEST, "stencil_spline": FLOPS_SPLINE,
+                                   "local_rotation": FLOPS_ROTATE},
+                     "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
+                     "gather": {"achieved_GB_per_s": gather / 1e9,
+                                "yardstick": "l2_gather_16B",
+                                "yardstick_GB_per_s": yard["l2_gather_16B"]["GB_per_s"] if yard else None,
+                                "frac": gather / (yard["l2_gather_16B"]["GB_per_s"] * 1e9) if yard else None},
+                     "dense_equivalent": {"pairs_per_launch": dense_pairs,
+                                          "note": "every changed pair of the rectangle counted, culled or "
+                                                  "not; not executed work"}},
+        "yardsticks": yard,
+        "energy": {"V_ref": r["V_ref"], "target_1.05_V_ref": r["target_ref"],
                    "best_min": float(r["v"][:, 1].min()), "best_median": float(np.median(r["v"][:, 1])),
-                   "chains_reaching_target": int(reached.size),
-                   "first_sweep_to_target": int(reached.min()) if reached.size else None},
+                   "chains_reaching_1.05_V_ref": int((r["v"][:, 1] <= r["target_ref"]).sum())},
     }
-    if rank == 0 and not args.no_cpu:
-        out["cpu_baseline"] = cpu_leg(w, host_cores(), args.cpu_sweeps)
+    if target is not None:
+        step = -(-first // cyc) if first is not None else None
+        out["time_to_target"] = {
+            "target": target, "target_kind": "mean lowest energy of the oracle runs (cpu_baseline)",
+            "chains_reaching": int(reached.size), "first_sweep": first,
+            "gpu_seconds": float(all_ms[:step].sum()) * 1e-3 if step else None,
+            "oracle_seconds_per_run_one_core": cpu["target_runs"]["seconds_per_run_one_core"],
+            "speedup_vs_one_core_run": (cpu["target_runs"]["seconds_per_run_one_core"]
+                                        / (float(all_ms[:step].sum()) * 1e-3)) if step else None}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -151,6 +151,18 @@ amh_status amh_set_trace(amh_ctx* ctx, int32_t n, const int32_t* chain_ids, doub
 amh_status amh_philox(const uint32_t* ctr_dev, int64_t n, uint64_t key, uint32_t* out_dev,
                       void* stream);
 
+/* Executed work of the global sweeps (the pair sums of the full energy, Sec. 2.3,
+ * evaluated as in Sec. 2.4: pair distances first, energies only where they count).
+ * counters_dev: int64[3] on the device, owned by the caller, or NULL to stop
+ * counting.  Every later amh_sweep adds, at the end of its launch:
+ *   [0] tiles of 8 x 8 residue pairs of the changed-pair rectangle that survive the
+ *       bounding-sphere test (the others hold only pairs beyond the last knot),
+ *   [1] pair distances tested inside the rectangle in those tiles,
+ *   [2] near pairs whose energy was evaluated (one 16-byte stencil each).
+ * The rest of the work is fixed by the schedule (localized pairs, candidate tiles,
+ * transitions, anchors) and needs no counting.  Stream-ordered like amh_sweep. */
+amh_status amh_set_work_counters(amh_ctx* ctx, int64_t* counters_dev);
+
 /* Synchronise the context stream and report asynchronous numeric errors
  * (AMH_E_NUMERIC) raised by earlier calls. */
 amh_status amh_poll(amh_ctx* ctx);

@@ -98,6 +98,7 @@ def lib():
         "amh_set_wait_bound": [_P, C.c_int32],
         "amh_set_trace": [_P, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, C.c_int64, _P, C.c_int64],
         "amh_poll": [_P],
+        "amh_set_work_counters": [_P, _P],
         "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
         "amh_grad": [_P, _P, C.c_int32, _P, _P],
@@ -117,6 +118,9 @@ def lib():
         "amh_submit": [_P, _P, C.POINTER(C.c_uint64)],
         "amh_destroy": [_P],
         "amh_philox": [_P, C.c_int64, C.c_uint64, _P, _P],
+        "amh_yard_stream": [_P, C.c_int64, C.c_int32, _P, _P],
+        "amh_yard_gather": [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P],
+        "amh_yard_lds": [C.c_int32, C.c_int32, _P, _P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -246,6 +250,15 @@ class Context:
     def energy_fn(self):
         """V(s) as a differentiable function of s [B][2L] (torch.autograd)."""
         return lambda s: _Energy.apply(s, self)
+
+    def set_work_counters(self, counters: torch.Tensor | None) -> None:
+        """Count the executed work of later global sweeps into an int64[3] device tensor
+        (amh_set_work_counters): surviving tiles, pair tests, near pairs; None stops."""
+        if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 3
+                                     or not counters.is_cuda):
+            raise ValueError("counters must be an int64 CUDA tensor of 3 elements")
+        self._work_keep = counters
+        check(lib().amh_set_work_counters(self._h, _ptr(counters)))
 
     def get_state(self) -> dict:
         n, Cc, L = 2 * self.L, self.C, self.L
@@ -459,3 +472,50 @@ def philox(ctr: torch.Tensor, key: int, stream=None) -> torch.Tensor:
     out = torch.empty_like(ctr)
     check(lib().amh_philox(_ptr(ctr), ctr.shape[0], key, _ptr(out), _stream(stream)))
     return out
+
+
+def yardsticks(device="cuda:0", table_rows=44850, table_stride=40, max_bin=35, repeats=3) -> dict:
+    """Achievable bandwidths of the access patterns of the sweep kernel on this GPU
+    (include/amh_yardstick.h): HBM streaming read of 2 GiB, 16-byte gathers from an
+    L2-resident table of the given padded shape (the 300-residue distogram by
+    default), LDS float4 reads.  Best of `repeats` timed launches each, GB/s."""
+    dev = torch.device(device)
+    st = torch.cuda.current_stream(dev)
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    out = {}
+
+    def best(fn, nbytes):
+        fn()   # warm
+        ms = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            torch.cuda.synchronize(dev)
+            ms.append(e0.elapsed_time(e1))
+        return nbytes / (min(ms) * 1e-3) / 1e9, min(ms)
+
+    nf4 = (2 << 30) // 16
+    src = torch.ones(nf4 * 4, dtype=torch.float32, device=dev)
+    blocks = 16 * n_cu
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    gbs, ms = best(lambda: check(lib().amh_yard_stream(_ptr(src), nf4, blocks, _ptr(sink), _stream(st))),
+                   16 * nf4)
+    out["hbm_stream_read"] = {"GB_per_s": gbs, "bytes": 16 * nf4, "ms": ms}
+    del src
+    table = torch.rand(table_rows * table_stride, dtype=torch.float32, device=dev)
+    per_thread, gblocks = 256, 32 * n_cu
+    sink = torch.empty(gblocks * 256, dtype=torch.float32, device=dev)
+    nbytes = 16 * gblocks * 256 * per_thread
+    gbs, ms = best(lambda: check(lib().amh_yard_gather(_ptr(table), table_rows, table_stride, max_bin,
+                                                       per_thread, gblocks, _ptr(sink), _stream(st))), nbytes)
+    out["l2_gather_16B"] = {"GB_per_s": gbs, "gathers_per_s": gbs * 1e9 / 16,
+                            "table_bytes": table_rows * table_stride * 4, "ms": ms}
+    lblocks, lper = 2 * n_cu, 4096
+    sink = torch.empty(lblocks * 512, dtype=torch.float32, device=dev)
+    nbytes = 16 * lblocks * 512 * lper
+    gbs, ms = best(lambda: check(lib().amh_yard_lds(lper, lblocks, _ptr(sink), _stream(st))), nbytes)
+    out["lds_read_16B"] = {"GB_per_s": gbs, "ms": ms}
+    return out
+

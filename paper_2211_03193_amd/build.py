@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libamh.so")
-SOURCES = ["csrc/amh_kernels.hip", "csrc/amh_grad.hip", "csrc/amh_api.hip", "csrc/amh_server.hip"]
+SOURCES = ["csrc/amh_kernels.hip", "csrc/amh_grad.hip", "csrc/amh_api.hip", "csrc/amh_server.hip",
+           "csrc/amh_yardstick.hip"]
 
 
 def hipcc() -> str:

@@ -84,6 +84,8 @@ struct amh_ctx {
   size_t work_n = 0;
   // this device's copy of the library's fixed scratch array (amh_minimize_noalloc)
   double* scratch = nullptr;
+  // caller's executed-work counters of the global sweeps (amh_set_work_counters)
+  unsigned long long* work_counters = nullptr;
 };
 
 // Fixed scratch of amh_minimize_noalloc: the L-BFGS workspace of callers that cannot
@@ -262,6 +264,7 @@ amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   P.tr_anchor = x->tr_anchor;
   P.trace_anchor_cap = x->trace_anchor_cap;
   P.trace_anchor0 = x->trace_anchor0;
+  P.work = x->work_counters;
   return P;
 }
 
@@ -595,6 +598,12 @@ amh_status amh_set_trace(amh_ctx* x, int32_t n, const int32_t* chain_ids, double
   x->tr_anchor = anchor_dev;
   x->trace_anchor_cap = anchor_capacity;
   x->trace_anchor0 = x->t / x->cfg.anchor_every + 1;
+  return AMH_OK;
+}
+
+amh_status amh_set_work_counters(amh_ctx* x, int64_t* counters_dev) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  x->work_counters = reinterpret_cast<unsigned long long*>(counters_dev);
   return AMH_OK;
 }
 

@@ -44,6 +44,10 @@ struct SweepParams {
   int64_t trace_cap, trace_t0;
   double* tr_anchor;
   int64_t trace_anchor_cap, trace_anchor0;
+  // executed-work counters of the global sweeps, or null: [0] rectangle tiles that
+  // survive the bounding-sphere test, [1] pair tests inside the rectangle in those
+  // tiles, [2] near pairs evaluated (one stencil each); added to at the end of a launch
+  unsigned long long* work;
 };
 
 struct ConfParams {

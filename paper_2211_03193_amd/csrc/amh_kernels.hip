@@ -582,6 +582,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
   const int nstage = W, stage = wave;
   const int lslot = (lane / (64 / G)) < nact ? trace_slot(P, c0 + lane / (64 / G)) : -1;
   int64_t acc_local_stage = 0;   // accepted localized proposals of this lane's chain
+  // executed work of this wavefront's share of the global sweeps (uniform)
+  unsigned int wk_tiles = 0, wk_tests = 0, wk_near = 0;
   bool stalled = false;
   const int64_t t_end = P.t0 + P.n_sweeps;
   for (int64_t t = P.t0; t < t_end;) {
@@ -726,6 +728,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
             while (m) {
               const int l = __builtin_ctzll(m);
               m &= m - 1;
+              ++wk_tiles;
               const int cd = __builtin_amdgcn_readlane(code, l);
               const int g = cd >> 16, i = 8 * ((cd >> 8) & 255) + lr, j = 8 * (cd & 255) + lc;
               const bool ok = i < p && j >= p && j < L;
@@ -734,9 +737,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
               const float q = dx * dx + dy * dy + dz * dz;
               const float d2 = ok ? q : 3.0e38f;
               const bool near = d2 < P.d2far;
+              wk_tests += (unsigned int)__popcll(__ballot(ok));
               const unsigned long long bal = __ballot(near);
               if (bal == 0ull) continue;
               const int cs = (int)__popcll(bal);
+              wk_near += (unsigned int)cs;
               const int rank = (int)__builtin_amdgcn_mbcnt_hi(
                   (unsigned int)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned int)bal, 0u));
               const uint2 e = make_uint2((unsigned int)i | ((unsigned int)j << 10) | ((unsigned int)g << 20),
@@ -885,6 +890,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
     ++t;
   }
 
+  if (P.work && lane == 0) {
+    atomicAdd(P.work + 0, (unsigned long long)wk_tiles);
+    atomicAdd(P.work + 1, (unsigned long long)wk_tests);
+    atomicAdd(P.work + 2, (unsigned long long)wk_near);
+  }
   // store chain state; the localized-sweep accept counts of a chain's waves are summed
   __syncthreads();
   if ((lane & (64 / G - 1)) == 0) S.nacc(W)[wave * G + lane / (64 / G)] = acc_local_stage;

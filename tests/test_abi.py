@@ -7,11 +7,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "amh.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("amh.h", "amh_yardstick.h")]
 
 
 def declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:amh_status|const char\*)\s+(amh_\w+)\s*\(", text, re.M)))
 
 
