@@ -73,9 +73,18 @@ struct Rot {
   double log_u;  // acceptance log-uniform of the proposal the rotation belongs to
 };
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps (float64).
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+
 __device__ __forceinline__ void make_rot(D3 A, D3 B, double c, double s, Rot& R) {
   double ux = B.x - A.x, uy = B.y - A.y, uz = B.z - A.z;
-  const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+  const double inv = rsqrt64(ux * ux + uy * uy + uz * uz);
   ux *= inv; uy *= inv; uz *= inv;
   const double t = 1.0 - c;
   R.r[0] = c + t * ux * ux;      R.r[1] = t * ux * uy - s * uz; R.r[2] = t * ux * uz + s * uy;
@@ -95,7 +104,7 @@ __device__ __forceinline__ void make_rot_u(D3 A, D3 u, double c, double s, Rot& 
 
 __device__ __forceinline__ D3 unit(D3 A, D3 B) {
   const double ux = B.x - A.x, uy = B.y - A.y, uz = B.z - A.z;
-  const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+  const double inv = rsqrt64(ux * ux + uy * uy + uz * uz);
   return D3{ux * inv, uy * inv, uz * inv};
 }
 

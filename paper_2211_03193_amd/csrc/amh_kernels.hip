@@ -403,7 +403,8 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int nact, int c0
     const bool live = k != 0 && k != n - 1;
     const int nF = p - lo > 0 ? p - lo : 0, nM = hi - p + 1 > 0 ? hi - p + 1 : 0;
     const int npair = live ? nF * nM : 0;
-    const float inv_nM = 1.0f / (float)(nM > 0 ? nM : 1);
+    // hardware reciprocal (1 ulp): floor((x + 1/2) inv_nM) stays exact for x < 2^22
+    const float inv_nM = __builtin_amdgcn_rcpf((float)(nM > 0 ? nM : 1));
     double part = 0.0;
     Rot Rk;
     // the changed pairs (lo + a, p + b), a in [0, nF), b in [0, nM), in passes of LW R:
@@ -665,10 +666,12 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
             }
             S.w32(g)[r] = make_float4(vx, vy, vz, 0.0f);
           }
-          const float cnt = sum8(real ? 1.0f : 0.0f), inv = 1.0f / (cnt > 1.0f ? cnt : 1.0f);
+          // any centre will do (the radius is measured from it); the 0.05 A margin of the
+          // tile test covers the 1-ulp hardware square root
+          const float cnt = sum8(real ? 1.0f : 0.0f), inv = __builtin_amdgcn_rcpf(cnt > 1.0f ? cnt : 1.0f);
           const float cx = sum8(vx) * inv, cy = sum8(vy) * inv, cz = sum8(vz) * inv;
-          const float rad = max8(real ? sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) +
-                                              (vz - cz) * (vz - cz))
+          const float rad = max8(real ? __builtin_amdgcn_sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) +
+                                                               (vz - cz) * (vz - cz))
                                       : 0.0f);
           if (g < nact && (r & 7) == 0) S.sph(W, g)[r >> 3] = make_float4(cx, cy, cz, rad);
         }
