@@ -244,10 +244,35 @@ def batch_leg(steps, warmup, n_proteins, tune_sweeps):
     }
 
 
-def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
+def cpu_serve_targets(jobs, runs, cores):
+    """CPU baseline of the serving workload (Sec. 3, Fig. 4E protocol): for every job,
+    `runs` oracle runs of the job's own schedule and sweep budget (one chain each,
+    from the extended chain); the mean of their lowest energies is the target that
+    job's device chains must reach.  Jobs run in parallel over the host cores."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(job):
+        w, y32 = job
+        ch = oracle.Chains(oracle.make_cfg(w), np.asarray(y32, dtype=np.float64),
+                           np.full((runs, 2 * w.L), math.pi), chain_ids=np.arange(runs, dtype=np.uint32))
+        t0 = time.perf_counter()
+        ch.run(w.total_sweeps, mode=1, threads=runs)
+        return float(np.mean(ch.v[:, 1])), (time.perf_counter() - t0)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=max(1, cores // runs)) as ex:
+        res = list(ex.map(one, jobs))
+    return [r[0] for r in res], [r[1] for r in res], time.perf_counter() - t0
+
+
+def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan, target_runs=3):
     """Poisson arrivals of folding jobs (L uniform on [50, 800], 64-512 chains, their
-    own Philox keys, target 1.05 V(s_ref)), served by continuous batching and by a
-    one-job-at-a-time queue; every job's best states must agree between the two."""
+    own Philox keys), served by continuous batching and by a one-job-at-a-time queue;
+    every job's best states must agree between the two.  A job ends when a chain
+    reaches its target, the mean lowest energy of `target_runs` oracle runs of the
+    same job on the host (the paper's time-to-solution protocol), or after its last
+    sweep; 1.05 V(s_ref) is reported beside it."""
     import torch
     from paper_2211_03193_amd import amh, serving
 
@@ -257,7 +282,7 @@ def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     chains = rng.choice([64, 128, 256, 512], size=n_jobs)
     arrivals = sy.poisson_arrivals(rate, n_jobs, seed + 2)
-    jobs = []
+    jobs, wl, vrefs = [], [], []
     for i, (L, C) in enumerate(zip(Ls, chains)):
         w = sy.Workload(f"job{i:02d}-L{int(L)}", L=int(L), n_chains=int(C), total_sweeps=sweeps,
                         window_d=12, seed=(seed << 16) + i, protein_seed=3000 + i, noise_seed=4000 + i)
@@ -268,14 +293,21 @@ def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
         probe = amh.Context(amh.make_config(w.replace(n_chains=1)), torch.from_numpy(y).to(dev))
         v_ref = probe.energy(torch.from_numpy(s_ref[None]).to(dev))[0].item()
         probe.close()
-        jobs.append((amh.make_config(w), y, 1.05 * v_ref))
+        wl.append((w, y))
+        vrefs.append(v_ref)
     torch.cuda.synchronize()
+    cpu_targets, cpu_secs, cpu_wall = cpu_serve_targets(wl, target_runs, host_cores())
+    for (w, y), tg in zip(wl, cpu_targets):
+        jobs.append((amh.make_config(w), y, tg))
     out = {}
     results = {}
     # round_pairs: a job advances sweeps_per_round * clamp(5e10 / (its pair evaluations per
     # round), 1, 64) sweeps per round, so small jobs keep pace with large ones
-    modes = (("continuous", 1 << 30, 50_000_000_000), ("continuous_lockstep", 1 << 30, 0),
-             ("fifo", 1, 50_000_000_000))
+    # continuous: the server's default, every admitted job advances sweeps_per_round per
+    # round; continuous_per_job_counts: a job's sweeps per round scale with its size
+    # (round_pairs); fifo: one job at a time
+    modes = (("continuous", 1 << 30, 0), ("continuous_per_job_counts", 1 << 30, 50_000_000_000),
+             ("fifo", 1, 0))
     for name, max_active, rp in modes:
         srv = amh.Server(int(budget_gib * 2**30), max_active=max_active,
                          sweeps_per_round=sweeps_per_round, plan=plan, round_pairs=rp)
@@ -286,25 +318,36 @@ def serve_leg(n_jobs, rate, sweeps, budget_gib, sweeps_per_round, plan):
         props = sum(s["sweeps"] * jobs[i][0].n_chains * 2 * jobs[i][0].L for i, s in enumerate(st))
         out[name]["proposals_per_s"] = props / out[name]["makespan_s"] if done else 0.0
         results[name] = [srv.job(s["id"], want_state=True) if s["state"] == 2 else None for s in st]
+        out[name]["reached_1.05_V_ref"] = int(sum(
+            1 for r, v in zip(results[name], vrefs) if r is not None and r["v"][:, 1].min() <= 1.05 * v))
         srv.close()
     same = all(a is not None and b is not None and np.array_equal(a["s_best"], b["s_best"])
                and np.array_equal(a["v"], b["v"])
                for a, b in zip(results["continuous"], results["fifo"]))
-    lock = out["continuous_lockstep"]
+    per_job = out["continuous_per_job_counts"]
     c, f = out["continuous"], out["fifo"]
     return {
-        "metric": "p99 request latency", "value": c["p99_time_to_done_s"], "unit": "s",
+        "metric": "p99 time-to-target", "value": c["p99_time_to_target_s"], "unit": "s",
         "n_gpus": 1, "steps": n_jobs, "warmup": 0, "ms_per_step": None,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"serve-{n_jobs}jobs-poisson{rate:g}-L50-800-64to512chains",
                    "sweeps_per_job": sweeps, "sweeps_per_round": sweeps_per_round, "plan": plan,
-                   "hbm_budget_gib": budget_gib, "target": "1.05 V(s_ref)", "round_pairs": 5e10,
-                   "latency": "submit to completion (target reached or last sweep)"},
-        "continuous": c, "fifo": f, "continuous_lockstep": lock,
-        "p99_speedup_vs_fifo": (f["p99_time_to_done_s"] / c["p99_time_to_done_s"]
-                                if c["p99_time_to_done_s"] else None),
+                   "hbm_budget_gib": budget_gib,
+                   "target": f"mean lowest energy of {target_runs} oracle runs of the job (same "
+                             "schedule and sweep budget, one chain each)",
+                   "round_pairs": {"continuous": 0, "continuous_per_job_counts": 5e10, "fifo": 0},
+                   "time_to_target": "submit to the first anchor with a chain at or below the target"},
+        "continuous": c, "fifo": f, "continuous_per_job_counts": per_job,
+        "p99_time_to_target_speedup_vs_fifo": (f["p99_time_to_target_s"] / c["p99_time_to_target_s"]
+                                               if c["p99_time_to_target_s"] and f["p99_time_to_target_s"]
+                                               else None),
+        "p99_time_to_done_speedup_vs_fifo": (f["p99_time_to_done_s"] / c["p99_time_to_done_s"]
+                                             if c["p99_time_to_done_s"] else None),
         "same_results_alone_and_in_mix": bool(same),
+        "cpu_baseline": {"kind": "oracle", "cores": host_cores(), "runs_per_job": target_runs,
+                         "seconds_per_job_run_mean": float(np.mean(cpu_secs)),
+                         "wall_s": cpu_wall, "targets": cpu_targets, "V_ref": vrefs},
     }
 
 

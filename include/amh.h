@@ -260,10 +260,26 @@ typedef struct {
                                count depends only on the job and these options. */
 } amh_server_opts;
 
+/* Optional per-proposal trace of one chain of a served job: the server hands it to
+ * amh_set_trace when it admits the job, so the trace covers the job's sweeps from
+ * the first.  The device buffers are the caller's and must stay valid until the job
+ * is done; layouts and capacities as in amh_set_trace (one chain). */
+typedef struct {
+  int32_t chain;          /* chain of the job to trace, 0 <= chain < n_chains */
+  int32_t reserved;
+  double* dE_dev;         /* [capacity] */
+  double* delta_dev;      /* [capacity] */
+  uint8_t* acc_dev;       /* [capacity] */
+  int64_t capacity;       /* proposals, >= 1 */
+  double* anchor_dev;     /* [anchor_capacity] or NULL */
+  int64_t anchor_capacity;
+} amh_job_trace;
+
 typedef struct {
   amh_config cfg;        /* the job's run, with its own seed (Philox key) */
   const float* y_host;   /* [L(L-1)/2][n_bins] -ln p in host memory, copied by amh_submit */
   double target;         /* the job ends at the first anchor where a chain has V <= target */
+  const amh_job_trace* trace;   /* NULL, or a trace request (copied by amh_submit) */
 } amh_job;
 
 typedef struct {

@@ -58,8 +58,15 @@ class ServerOpts(C.Structure):
                 ("round_pairs", C.c_int64)]
 
 
+class JobTrace(C.Structure):
+    _fields_ = [("chain", C.c_int32), ("reserved", C.c_int32), ("dE_dev", C.c_void_p),
+                ("delta_dev", C.c_void_p), ("acc_dev", C.c_void_p), ("capacity", C.c_int64),
+                ("anchor_dev", C.c_void_p), ("anchor_capacity", C.c_int64)]
+
+
 class Job(C.Structure):
-    _fields_ = [("cfg", AmhConfig), ("y_host", C.c_void_p), ("target", C.c_double)]
+    _fields_ = [("cfg", AmhConfig), ("y_host", C.c_void_p), ("target", C.c_double),
+                ("trace", C.POINTER(JobTrace))]
 
 
 class JobStatus(C.Structure):
@@ -392,19 +399,42 @@ class Server:
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         self._h = C.c_void_p()
         self._cfg = {}
+        self._traces = {}
         check(lib().amh_server_create(C.byref(self.opts), _stream(self._stream_obj), C.byref(self._h)))
 
-    def submit(self, cfg: AmhConfig, y, target: float) -> int:
-        """Queue a job: cfg (amh_config), y [L(L-1)/2][n_bins] float32 host array, target V."""
+    def submit(self, cfg: AmhConfig, y, target: float, trace_chain: int | None = None) -> int:
+        """Queue a job: cfg (amh_config), y [L(L-1)/2][n_bins] float32 host array, target V.
+        With trace_chain, that chain's proposals are traced from the job's first sweep
+        (buffers sized for all its sweeps; read them with trace(job_id))."""
         import numpy as np
         y = np.ascontiguousarray(y, dtype=np.float32)
         if y.shape != (cfg.L * (cfg.L - 1) // 2, cfg.n_bins):
             raise ValueError(f"y has shape {y.shape}")
         job = Job(cfg=cfg, y_host=y.ctypes.data, target=float(target))
+        bufs = None
+        if trace_chain is not None:
+            dev = torch.cuda.current_device()
+            cap = int(cfg.total_sweeps) * 2 * cfg.L
+            acap = max(1, int(cfg.total_sweeps) // max(1, cfg.anchor_every))
+            bufs = {"dE": torch.full((cap,), float("nan"), dtype=torch.float64, device=dev),
+                    "delta": torch.full((cap,), float("nan"), dtype=torch.float64, device=dev),
+                    "acc": torch.full((cap,), 255, dtype=torch.uint8, device=dev),
+                    "anchor": torch.full((acap,), float("nan"), dtype=torch.float64, device=dev),
+                    "chain": int(trace_chain)}
+            tr = JobTrace(chain=int(trace_chain), reserved=0, dE_dev=_ptr(bufs["dE"]),
+                          delta_dev=_ptr(bufs["delta"]), acc_dev=_ptr(bufs["acc"]), capacity=cap,
+                          anchor_dev=_ptr(bufs["anchor"]), anchor_capacity=acap)
+            job.trace = C.pointer(tr)
         jid = C.c_uint64()
         check(lib().amh_submit(self._h, C.byref(job), C.byref(jid)))
         self._cfg[jid.value] = (cfg.n_chains, cfg.L)
+        if bufs is not None:
+            self._traces[jid.value] = bufs
         return jid.value
+
+    def trace(self, jid: int) -> dict:
+        """The trace buffers of a traced job (device tensors; valid once it is done)."""
+        return self._traces[jid]
 
     def step(self) -> tuple[int, int]:
         a, p = C.c_int32(), C.c_int32()

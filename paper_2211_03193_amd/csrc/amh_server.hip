@@ -31,7 +31,8 @@
 #include "amh_error.h"
 
 static_assert(sizeof(amh_server_opts) == 32, "amh_server_opts layout");
-static_assert(sizeof(amh_job) == 136, "amh_job layout");
+static_assert(sizeof(amh_job) == 144, "amh_job layout");
+static_assert(sizeof(amh_job_trace) == 56, "amh_job_trace layout");
 static_assert(sizeof(amh_job_status) == 72, "amh_job_status layout");
 
 namespace {
@@ -66,6 +67,8 @@ struct Job {
   std::vector<double> s_best;  // [C][2L] host copy at completion
   std::vector<double> v;       // [C][2]
   std::string error;
+  bool traced = false;
+  amh_job_trace trace{};
 };
 
 }  // namespace
@@ -121,6 +124,11 @@ amh_status admit(amh_server* s, Job* j) {
   (void)hipStreamSynchronize(s->stream);
   (void)hipFree(y_dev);
   if (st == AMH_OK && (st = amh_set_target(j->ctx, j->target)) != AMH_OK) j->error = amh_last_error();
+  if (st == AMH_OK && j->traced &&
+      (st = amh_set_trace(j->ctx, 1, &j->trace.chain, j->trace.dE_dev, j->trace.delta_dev,
+                          j->trace.acc_dev, j->trace.capacity, j->trace.anchor_dev,
+                          j->trace.anchor_capacity)) != AMH_OK)
+    j->error = amh_last_error();
   if (st != AMH_OK) {
     if (j->ctx) (void)amh_destroy(j->ctx);
     j->ctx = nullptr;
@@ -188,7 +196,18 @@ amh_status amh_submit(void* server, const void* job, uint64_t* job_id) {
     return sfail(AMH_E_INVAL, "job configuration out of range");
   if (!jb->y_host) return sfail(AMH_E_INVAL, "job table is NULL");
   if (std::isnan(jb->target)) return sfail(AMH_E_INVAL, "target is NaN");
+  if (jb->trace) {
+    const amh_job_trace& tr = *jb->trace;
+    if (tr.chain < 0 || tr.chain >= c.n_chains) return sfail(AMH_E_INVAL, "trace chain out of range");
+    if (!tr.dE_dev || !tr.delta_dev || !tr.acc_dev || tr.capacity < 1)
+      return sfail(AMH_E_INVAL, "trace buffers missing or capacity < 1");
+    if (tr.anchor_dev && tr.anchor_capacity < 1) return sfail(AMH_E_INVAL, "anchor capacity < 1");
+  }
   auto j = std::make_unique<Job>();
+  if (jb->trace) {
+    j->traced = true;
+    j->trace = *jb->trace;
+  }
   j->id = s->next_id++;
   j->cfg = c;
   j->target = jb->target;

@@ -114,7 +114,9 @@ def test_server_calls_reject_null_arguments(amh):
 
 def test_server_struct_layouts(amh):
     assert C.sizeof(amh.ServerOpts) == 32 and amh.ServerOpts.round_pairs.offset == 24
-    assert C.sizeof(amh.Job) == 120 + 8 + 8 and amh.Job.target.offset == 128
+    assert C.sizeof(amh.Job) == 120 + 8 + 8 + 8 and amh.Job.target.offset == 128
+    assert amh.Job.trace.offset == 136 and C.sizeof(amh.JobTrace) == 56
+    assert amh.JobTrace.capacity.offset == 32 and amh.JobTrace.anchor_capacity.offset == 48
     assert C.sizeof(amh.JobStatus) == 72 and amh.JobStatus.best_V.offset == 24
 
 

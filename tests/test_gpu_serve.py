@@ -126,3 +126,39 @@ def test_admission_respects_the_memory_budget():
     assert all(s["state"] == 2 for s in st)
     assert held_back
     srv.close()
+
+
+def test_served_chain_replays_against_the_oracle():
+    """One chain of a job served in a mix (admitted while others run, its sweeps in
+    shared launches) is traced through the job's trace option and replayed proposal
+    by proposal by the oracle from the job's start."""
+    gu.say("served traced chain vs oracle")
+    from paper_2211_03193_amd import amh
+    jobs = _jobs()
+    traced = 3                          # L = 70, never reaches 1.05 V_ref in its sweeps
+    chain = 2
+    srv = amh.Server(hbm_budget_bytes=64 << 20, max_active=3, sweeps_per_round=5, round_pairs=3_000_000)
+    ids = [srv.submit(cfg, y, tg, trace_chain=chain if i == traced else None)
+           for i, (_, cfg, y, tg) in enumerate(jobs)]
+    rounds = 0
+    while True:
+        a, p = srv.step()
+        rounds += 1
+        if a == 0 and p == 0:
+            break
+        assert rounds < 1000
+    st = srv.job(ids[traced])
+    assert st["state"] == 2
+    w, _, y, _ = jobs[traced]
+    n_sw = int(st["sweeps"])
+    assert n_sw >= 10
+    b = srv.trace(ids[traced])
+    torch.cuda.synchronize()
+    tr = {"n_sweeps": n_sw, "dE": b["dE"].cpu().numpy()[None], "delta": b["delta"].cpu().numpy()[None],
+          "acc": b["acc"].cpu().numpy()[None], "anchor": b["anchor"].cpu().numpy()[None]}
+    n = n_sw * 2 * w.L
+    assert np.all(np.isfinite(tr["dE"][0, :n])) and np.all(tr["acc"][0, :n] <= 1)
+    rc, rep, _ = gu.replay_chain(w, y.astype(np.float64), tr, 0, chain, gu.extended(w))
+    assert rc == 0 and rep["n_de_fail"] == 0 and rep["n_logic_fail"] == 0, rep
+    assert rep["n_forks"] <= max(1, int(1e-4 * n)), rep
+    srv.close()
