@@ -183,10 +183,17 @@ __global__ void conf_energy_kernel(ConfParams P) {
 // torsions [2L]; then the rotation slots of the current and next proposal per
 // chain, the wavefront partials, the anchor scratch, the near-pair queues and the
 // bounding spheres of the rectangle's tiles.
+__host__ __device__ inline size_t chain_stride(int L) {
+  const size_t b = 128 * (size_t)L;
+  return b + ((64 + 256 - (b & 255)) & 255);
+}
+
 struct Lds {
   unsigned char* base;
   int L, G;
-  __device__ size_t per() const { return 128 * (size_t)L; }
+  // per-chain stride: 128 L bytes padded to 64 mod 256, so that the same residue of
+  // the G chains (read together by the localized sweeps) falls in different banks
+  __device__ size_t per() const { return chain_stride(L); }
   __device__ double* x64(int g) const { return reinterpret_cast<double*>(base + g * per()); }
   __device__ float4* w32(int g) const { return reinterpret_cast<float4*>(base + g * per() + 96 * (size_t)L); }
   __device__ double* s(int g) const { return reinterpret_cast<double*>(base + g * per() + 112 * (size_t)L); }
@@ -212,7 +219,7 @@ struct Lds {
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
-  return (size_t)G * 128 * L + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
+  return (size_t)G * chain_stride(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
          8 * (size_t)G + 4 * (size_t)((W + 1) & ~1) + 8 * (size_t)W * G + 64 + 16 +
          8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8);
 }
