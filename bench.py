@@ -507,6 +507,107 @@ def tts_leg(cpu_runs, chains):
     }
 
 
+# float64 operations of one pair of the gradient's force pass: distance (3 sub, 3 mul,
+# 2 add, sqrt), spline value and derivative (~24), force and torque accumulation (~15)
+FLOPS_GRAD_PAIR = 48.0
+
+
+def hybrid_leg(cycles=2, lbfgs_iters=200, amh_sweeps=500, chains=512, L=400):
+    """Differentiation + hybrid: L-BFGS phases (amh_minimize, the adjoint gradient in
+    every line-search trial) interleaved with AMH phases on the same chains, against
+    plain AMH over the same sweeps.  Synthetic 400-residue protein, 512 chains.  The
+    time-to-target is the time the hybrid needs to reach plain AMH's final lowest
+    energy.  The gradient kernel's force pass is also timed alone for its roofline."""
+    import torch
+    from paper_2211_03193_amd import amh, hybrid
+
+    dev = torch.device("cuda:0")
+    w = sy.Workload("hybrid-L400", L=L, n_chains=chains, total_sweeps=cycles * amh_sweeps, window_d=12,
+                    global_every=10, sigma_deg=10.0, T0=1.0, T1=0.01, seed=0x414D4804,
+                    protein_seed=4, noise_seed=104)
+    s_ref = sy.reference_torsions(w.L, w.protein_seed)
+    atoms = amh.conformation(torch.from_numpy(s_ref[None]).to(dev))[0].cpu().numpy()
+    y = torch.from_numpy(np.ascontiguousarray(
+        sy.distogram(sy.pair_distances(atoms[:, 3, :]), w.eps, w.noise_seed), dtype=np.float32)).to(dev)
+    st = torch.cuda.current_stream()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        return e
+
+    # plain AMH over the whole schedule
+    plain = amh.Context(amh.make_config(w), y)
+    V_ref = plain.energy(torch.from_numpy(s_ref[None]).to(dev))[0].item()
+    e0 = ev()
+    plain.sweep(w.total_sweeps)
+    e1 = ev()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) * 1e-3
+    best_plain = plain.energy(which=1)[0].min().item()
+    plain.close()
+    # hybrid: AMH phase, then L-BFGS phase, repeated
+    ctx = amh.Context(amh.make_config(w), y)
+    opts = amh.lbfgs_opts(n_iter=lbfgs_iters)
+    phases, t_total, t_target = [], 0.0, None
+    for c in range(cycles):
+        for kind in ("amh", "lbfgs"):
+            e0 = ev()
+            if kind == "amh":
+                ctx.sweep(amh_sweeps)
+            else:
+                out = hybrid.lbfgs_with_localized_mh(ctx, cycles=1, lbfgs_iters=lbfgs_iters, mh_sweeps=0,
+                                                     opts=opts, final_lbfgs=False)[0]
+            e1 = ev()
+            torch.cuda.synchronize()
+            dt = e0.elapsed_time(e1) * 1e-3
+            t_total += dt
+            vb = ctx.energy(which=1)[0]
+            rec = {"cycle": c, "phase": kind, "seconds": dt, "best_min": vb.min().item(),
+                   "best_median": vb.median().item()}
+            if kind == "lbfgs":
+                rec["iterations_mean"] = out["iters"].double().mean().item()
+                rec["status_counts"] = {str(k): int((out["status"] == k).sum().item()) for k in (0, 1, 2)}
+            else:
+                rec["proposals_per_s"] = chains * amh_sweeps * 2 * L / dt
+            phases.append(rec)
+            if t_target is None and rec["best_min"] <= best_plain:
+                t_target = t_total
+    best_hybrid = ctx.energy(which=1)[0].min().item()
+    # the adjoint gradient alone: V and dV/ds of the 512 current conformations
+    s_now = ctx.get_state()["s"].contiguous()
+    ctx.grad(s_now)
+    reps = 20
+    e0 = ev()
+    for _ in range(reps):
+        ctx.grad(s_now)
+    e1 = ev()
+    torch.cuda.synchronize()
+    g_s = e0.elapsed_time(e1) * 1e-3 / reps
+    ctx.close()
+    pairs = chains * L * (L - 1) // 2
+    achieved = FLOPS_GRAD_PAIR * pairs / g_s
+    return {
+        "metric": "time-to-target-energy vs plain AMH", "value": (t_plain / t_target) if t_target else None,
+        "unit": "x", "n_gpus": 1, "steps": cycles, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hybrid-L{L}-{chains}chains", "cycles": cycles, "amh_sweeps": amh_sweeps,
+                   "lbfgs_iterations": lbfgs_iters, "window_d": 12, "global_every": 10,
+                   "sigma_deg": 10.0, "T": [1.0, 0.01], "lbfgs": {"m": opts.m, "nonmonotone": opts.nonmonotone,
+                                                                "c1": opts.c1, "max_ls": opts.max_ls},
+                   "orientation_terms": "not built (the paper does not define them)"},
+        "target": best_plain, "target_kind": "plain AMH's lowest energy after the same sweeps",
+        "V_ref": V_ref, "plain_seconds": t_plain, "hybrid_seconds": t_total,
+        "hybrid_seconds_to_target": t_target, "best_plain": best_plain, "best_hybrid": best_hybrid,
+        "phases": phases,
+        "gradient": {"conformations": chains, "ms_per_call": g_s * 1e3, "pairs_per_call": pairs,
+                     "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": 78.6432,
+                                  "unit": "TFLOP/s (float64)", "frac": achieved / 78.6432e12,
+                                  "flops_per_pair": FLOPS_GRAD_PAIR}},
+    }
+
+
 def cpu_leg(w, cores, sweeps, one_core_sweeps=200, target_runs=10, target_proposals=100000):
     """The float64 oracle on the host: (a) all `cores` threads, two chains each, for
     `sweeps` sweeps of the workload from the extended chain; (b) one thread, two
@@ -565,7 +666,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU-baseline leg")
     ap.add_argument("--no-yardsticks", action="store_true",
                     help="skip the achievable-bandwidth yardsticks of the roofline")
-    ap.add_argument("--workload", choices=["single", "batch", "serve", "variants", "tts"],
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "variants", "tts", "hybrid"],
                     default="single",
                     help="single: one L=300 protein, 1024 chains (default); batch: 64 proteins "
                          "of lengths 50-600, 256 chains each, batched vs plain launches; serve: "
@@ -596,9 +697,11 @@ def main():
               "GPUs with no per-step communication, see the design notes.", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    if args.workload in ("batch", "serve", "variants", "tts"):
+    if args.workload in ("batch", "serve", "variants", "tts", "hybrid"):
         if args.workload == "tts":
             out = tts_leg(10, 1024)
+        elif args.workload == "hybrid":
+            out = hybrid_leg()
         elif args.workload == "batch":
             out = batch_leg(args.steps, args.warmup, args.proteins, args.tune_sweeps)
         elif args.workload == "serve":
