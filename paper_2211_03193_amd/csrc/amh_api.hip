@@ -450,25 +450,31 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
     return sfail(AMH_E_INVAL, "sweep %lld + %lld passes total_sweeps=%lld", (long long)x->t,
                 (long long)n_sweeps, (long long)x->cfg.total_sweeps);
   if (n_sweeps == 0) return AMH_OK;
-  const amh::SweepParams P = sweep_params(x, n_sweeps);
+  const amh::SweepParams P0 = sweep_params(x, n_sweeps);
   const amh_config& c = x->cfg;
   const dim3 grid((c.n_chains + x->G - 1) / x->G), block(64 * x->W);
-  switch (x->G) {
-    case 1:
-      HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_kernel<1>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)x->lds));
-      hipLaunchKernelGGL(amh::sweep_kernel<1>, grid, block, x->lds, x->stream, P);
-      break;
-    case 2:
-      HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_kernel<2>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)x->lds));
-      hipLaunchKernelGGL(amh::sweep_kernel<2>, grid, block, x->lds, x->stream, P);
-      break;
-    default:
-      HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_kernel<4>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)x->lds));
-      hipLaunchKernelGGL(amh::sweep_kernel<4>, grid, block, x->lds, x->stream, P);
-      break;
+  // one launch per run of sweeps of one kind (localized or global), in order on the
+  // stream; a launch boundary between two sweeps does not change any result
+  for (int64_t t = P0.t0; t < P0.t0 + P0.n_sweeps;) {
+    const bool glob = amh::is_global(P0, t);
+    int64_t e = t + 1;
+    while (e < P0.t0 + P0.n_sweeps && amh::is_global(P0, e) == glob) ++e;
+    amh::SweepParams P = P0;
+    P.t0 = t;
+    P.n_sweeps = e - t;
+    const void* fn = nullptr;
+    switch (x->G) {
+      case 1: fn = glob ? (const void*)amh::sweep_kernel<1, amh::kSweepGlobal>
+                        : (const void*)amh::sweep_kernel<1, amh::kSweepLocal>; break;
+      case 2: fn = glob ? (const void*)amh::sweep_kernel<2, amh::kSweepGlobal>
+                        : (const void*)amh::sweep_kernel<2, amh::kSweepLocal>; break;
+      default: fn = glob ? (const void*)amh::sweep_kernel<4, amh::kSweepGlobal>
+                         : (const void*)amh::sweep_kernel<4, amh::kSweepLocal>; break;
+    }
+    HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)x->lds));
+    void* args[] = {&P};
+    HIP_OK(hipLaunchKernel(fn, grid, block, args, x->lds, x->stream));
+    t = e;
   }
   HIP_OK(hipGetLastError());
   x->t += n_sweeps;

@@ -71,6 +71,15 @@ struct ConfParams {
 };
 
 size_t sweep_lds_bytes(int G, int L, int W);
+
+// Sweep t is global iff it is one of the last n_global sweeps of its cycle of
+// global_every sweeps (Algorithm 1's alternation, localized sweeps first).
+__host__ __device__ inline bool is_global(const SweepParams& P, int64_t t) {
+  return P.global_every > 0 && (int)((uint32_t)t % (uint32_t)P.global_every) >= P.global_every - P.n_global;
+}
+
+// kinds of sweep a sweep kernel instance runs
+constexpr int kSweepMixed = 0, kSweepLocal = 1, kSweepGlobal = 2;
 inline size_t conf_lds_bytes(int L, int W) {
   return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)W + 2) + 32;
 }
@@ -81,7 +90,7 @@ __global__ void conf_energy_kernel(ConfParams P);
 __global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
 __global__ void perturb_kernel(double* s, int64_t n_total, int n, uint32_t chain_offset, uint32_t tag,
                                uint32_t k0, uint32_t k1, double amplitude);
-template <int G>
+template <int G, int MODE>
 __global__ void sweep_kernel(SweepParams P);
 template <int G>
 __global__ void sweep_batch_kernel(const SweepParams* descs, const int2* map);

@@ -242,11 +242,6 @@ __device__ __forceinline__ double sigma_at(const SweepParams& P, int64_t t) {
   return P.sigma;
 }
 
-// Sweep t is global iff it is one of the last n_global sweeps of its cycle of
-// global_every sweeps (Algorithm 1's alternation, localized sweeps first).
-__device__ __forceinline__ bool is_global(const SweepParams& P, int64_t t) {
-  return P.global_every > 0 && (int)((uint32_t)t % (uint32_t)P.global_every) >= P.global_every - P.n_global;
-}
 
 // Window half-width of localized sweep t: window_d, then the cascade radii in turn
 // (Sec. 2.2 allows several localization ranges).
@@ -546,10 +541,12 @@ __device__ __forceinline__ void add_chain(double* acc, int g, double v) {
 
 // The sweeps of one workgroup: chains group*G .. group*G + G-1 of the protein that P
 // describes, over sweeps [P.t0, P.t0 + P.n_sweeps).
-template <int G>
+template <int G, int MODE>
 __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int tid = threadIdx.x, T = blockDim.x, wave = tid >> 6, lane = tid & 63, W = T >> 6;
+  // (the localized-only instance holds the wavefront index in a scalar register)
+  const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, W = T >> 6;
+  const int wave = MODE == kSweepLocal ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
   const int L = P.L, n = 2 * L;
   const int c0 = group * G;
   const int nact = P.C - c0 < G ? P.C - c0 : G;
@@ -595,7 +592,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
   bool stalled = false;
   const int64_t t_end = P.t0 + P.n_sweeps;
   for (int64_t t = P.t0; t < t_end;) {
-    const bool global = is_global(P, t);
+    const bool global = MODE == kSweepLocal ? false : MODE == kSweepGlobal ? true : is_global(P, t);
     double T_t = P.T0;
     if (P.S > 1) T_t = P.T0 * pow(P.T1 / P.T0, (double)t / (double)(P.S - 1));
     const double beta = 1.0 / T_t;
@@ -721,13 +718,16 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
           };
           const int Ip = (p - 1) >> 3, Jp = p >> 3, nJ = nb8 - Jp, per = (Ip + 1) * nJ;
           const int ncand = nact * per;
+          const float inv_per = 1.0f / (float)per, inv_nJ = 1.0f / (float)nJ;
           const int lr = lane >> 3, lc = lane & 7;
           for (int base = 0; base < ncand; base += T) {
             const int cand = base + lane * W + wave;
             int code = 0;
             bool keep = false;
             if (cand < ncand) {
-              const int g = cand / per, rem = cand - g * per, I = rem / nJ, J = Jp + (rem - I * nJ);
+              // quotients through the float reciprocal, exact for operands below 2^21
+              const int g = (int)(((float)cand + 0.5f) * inv_per), rem = cand - g * per;
+              const int I = (int)(((float)rem + 0.5f) * inv_nJ), J = Jp + (rem - I * nJ);
               const float4 a = S.sph(W, g)[I], b = S.sph(W, g)[J];
               const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
               const float lim = rcut + a.w + b.w;
@@ -927,9 +927,12 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
   }
 }
 
-template <int G>
+// MODE kSweepLocal / kSweepGlobal: every sweep of [t0, t0 + n_sweeps) is localized /
+// global (the caller splits a range where the kind changes); each instance holds
+// only its kind of sweep, and so its own register allocation.
+template <int G, int MODE>
 __global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
-  sweep_body<G>(P, blockIdx.x);
+  sweep_body<G, MODE>(P, blockIdx.x);
 }
 
 // Several proteins in one launch: workgroup b runs chain group map[b].y of the
@@ -938,12 +941,15 @@ template <int G>
 __global__ __launch_bounds__(512) void sweep_batch_kernel(const SweepParams* __restrict__ descs,
                                                           const int2* __restrict__ map) {
   const int2 wm = map[blockIdx.x];
-  sweep_body<G>(descs[wm.x], wm.y);
+  sweep_body<G, kSweepMixed>(descs[wm.x], wm.y);
 }
 
-template __global__ void sweep_kernel<1>(SweepParams);
-template __global__ void sweep_kernel<2>(SweepParams);
-template __global__ void sweep_kernel<4>(SweepParams);
+template __global__ void sweep_kernel<1, kSweepLocal>(SweepParams);
+template __global__ void sweep_kernel<2, kSweepLocal>(SweepParams);
+template __global__ void sweep_kernel<4, kSweepLocal>(SweepParams);
+template __global__ void sweep_kernel<1, kSweepGlobal>(SweepParams);
+template __global__ void sweep_kernel<2, kSweepGlobal>(SweepParams);
+template __global__ void sweep_kernel<4, kSweepGlobal>(SweepParams);
 template __global__ void sweep_batch_kernel<1>(const SweepParams*, const int2*);
 template __global__ void sweep_batch_kernel<2>(const SweepParams*, const int2*);
 template __global__ void sweep_batch_kernel<4>(const SweepParams*, const int2*);
