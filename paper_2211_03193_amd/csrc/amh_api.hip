@@ -47,6 +47,7 @@ using amh::sfail;
   } while (0)
 
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kLocalWaves = 12;          // wavefronts of a localized-only sweep launch
 constexpr int kConfThreads = 256;
 
 int row_stride(int nb) { return ((nb + 2) + 3) & ~3; }   // nb values + 2 ghosts, 16-byte rows
@@ -453,6 +454,10 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
   const amh::SweepParams P0 = sweep_params(x, n_sweeps);
   const amh_config& c = x->cfg;
   const dim3 grid((c.n_chains + x->G - 1) / x->G), block(64 * x->W);
+  // localized sweeps run with kLocalWaves wavefronts (consecutive sweeps of a block
+  // pipelined over more stages) where their LDS fits
+  const int wl = amh::sweep_lds_bytes_local(x->G, c.L, kLocalWaves) <= kMaxLds ? kLocalWaves : x->W;
+  const size_t lds_l = amh::sweep_lds_bytes_local(x->G, c.L, wl);
   // one launch per run of sweeps of one kind (localized or global), in order on the
   // stream; a launch boundary between two sweeps does not change any result
   for (int64_t t = P0.t0; t < P0.t0 + P0.n_sweeps;) {
@@ -471,9 +476,10 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
       default: fn = glob ? (const void*)amh::sweep_kernel<4, amh::kSweepGlobal>
                          : (const void*)amh::sweep_kernel<4, amh::kSweepLocal>; break;
     }
-    HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)x->lds));
+    const size_t lds = glob ? x->lds : lds_l;
+    HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void* args[] = {&P};
-    HIP_OK(hipLaunchKernel(fn, grid, block, args, x->lds, x->stream));
+    HIP_OK(hipLaunchKernel(fn, grid, glob ? block : dim3(64 * wl), args, lds, x->stream));
     t = e;
   }
   HIP_OK(hipGetLastError());

@@ -71,6 +71,7 @@ struct ConfParams {
 };
 
 size_t sweep_lds_bytes(int G, int L, int W);
+size_t sweep_lds_bytes_local(int G, int L, int W);
 
 // Sweep t is global iff it is one of the last n_global sweeps of its cycle of
 // global_every sweeps (Algorithm 1's alternation, localized sweeps first).
@@ -80,8 +81,12 @@ __host__ __device__ inline bool is_global(const SweepParams& P, int64_t t) {
 
 // kinds of sweep a sweep kernel instance runs
 constexpr int kSweepMixed = 0, kSweepLocal = 1, kSweepGlobal = 2;
+// virtual wavefronts of the float64 energy reduction (fixed, so that the energy
+// does not depend on the launch shape)
+constexpr int kVirtWaves = 8;
 inline size_t conf_lds_bytes(int L, int W) {
-  return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)W + 2) + 32;
+  (void)W;
+  return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)kVirtWaves + 2) + 32;
 }
 
 __global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, float* out,

@@ -92,33 +92,39 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
 }
 
 // Float64 energy V = sum_{i<j} E_ij(|CB_i - CB_j|) of one conformation (C-beta read
-// from x64), each thread accumulating a Neumaier pair; the wavefronts' partials
-// are combined in a fixed order.  red64 holds 2 * nwaves doubles; the result is
-// written to *V_out by thread 0 and is visible after the final barrier.
+// from x64).  The pairs, in row-major order, are dealt round-robin to 64 kVirtWaves
+// virtual threads, each accumulating a Neumaier pair; the 64 virtual threads of a
+// virtual wavefront are reduced by shuffles and the kVirtWaves partials combined in
+// order, so that V does not depend on the launch shape (wavefront w of the launch
+// runs virtual wavefronts w, w + W, ...).  red64 holds 2 kVirtWaves doubles; the
+// result is written to *V_out by thread 0 and is visible after the final barrier.
 __device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min, double w,
                          int L, const double* __restrict__ x64, double* red64, double* V_out) {
-  const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
-  double sum = 0.0, cmp = 0.0;
-  int i = 0, j = 1 + tid;
-  while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
-  while (i < L - 1) {
-    const float* row = table + (size_t)pair_row(i, j, L) * stride;
-    const double* a = atom(x64, i, 3);
-    const double* b = atom(x64, j, 3);
-    const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-    neumaier_add(sum, cmp, spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w));
-    j += T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
+  constexpr int VT = 64 * kVirtWaves;
+  for (int vw = wave; vw < kVirtWaves; vw += W) {
+    double sum = 0.0, cmp = 0.0;
+    int i = 0, j = 1 + 64 * vw + lane;
     while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
+    while (i < L - 1) {
+      const float* row = table + (size_t)pair_row(i, j, L) * stride;
+      const double* a = atom(x64, i, 3);
+      const double* b = atom(x64, j, 3);
+      const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+      neumaier_add(sum, cmp, spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w));
+      j += VT;
+      while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double so = __shfl_down(sum, o, 64), co = __shfl_down(cmp, o, 64);
+      if (lane < o) { neumaier_add(sum, cmp, so); cmp += co; }
+    }
+    if (lane == 0) { red64[2 * vw] = sum; red64[2 * vw + 1] = cmp; }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const double so = __shfl_down(sum, o, 64), co = __shfl_down(cmp, o, 64);
-    if (lane < o) { neumaier_add(sum, cmp, so); cmp += co; }
-  }
-  if (lane == 0) { red64[2 * wave] = sum; red64[2 * wave + 1] = cmp; }
   __syncthreads();
   if (tid == 0) {
     double s = 0.0, c = 0.0;
-    for (int v = 0; v < W; ++v) { neumaier_add(s, c, red64[2 * v]); c += red64[2 * v + 1]; }
+    for (int v = 0; v < kVirtWaves; ++v) { neumaier_add(s, c, red64[2 * v]); c += red64[2 * v + 1]; }
     *V_out = s + c;
   }
   __syncthreads();
@@ -128,12 +134,12 @@ __device__ void energy64(const float* __restrict__ table, int stride, int nb, do
 // Conformation / energy kernel: one workgroup per conformation.
 __global__ void conf_energy_kernel(ConfParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const int L = P.L, tid = threadIdx.x, lane = tid & 63, W = blockDim.x >> 6;
+  const int L = P.L, tid = threadIdx.x, lane = tid & 63;
   const int b = blockIdx.x;
   double* s = reinterpret_cast<double*>(lds);   // [2L]
   double* x64 = s + 2 * L;                      // [12L]
-  double* red64 = x64 + 12 * L;                 // [2W]
-  double* Vs = red64 + 2 * W;                   // [1]
+  double* red64 = x64 + 12 * L;                 // [2 kVirtWaves]
+  double* Vs = red64 + 2 * kVirtWaves;          // [1]
   const double* src = P.s_in ? P.s_in + (size_t)b * 2 * L : nullptr;
   for (int m = tid; m < 2 * L; m += blockDim.x) s[m] = src ? src[m] : kPi;
   __syncthreads();
@@ -179,10 +185,10 @@ __global__ void conf_energy_kernel(ConfParams P) {
 
 // ---------------------------------------------------------------------------
 // LDS layout of a sweep workgroup: per chain (stride 128 L bytes) the float64
-// atoms [L][4][3], the float32 pivot-relative C-beta work array [L] and the
+// atoms [L][4][3], the float32 C-beta work array of global sweeps [L] and the
 // torsions [2L]; then the rotation slots of the current and next proposal per
-// chain, the wavefront partials, the anchor scratch, the near-pair queues and the
-// bounding spheres of the rectangle's tiles.
+// chain, the wavefront partials, the anchor scratch, the near-pair queues, the
+// bounding spheres of the rectangle's tiles and the work arrays' origins.
 __host__ __device__ inline size_t chain_stride(int L) {
   const size_t b = 128 * (size_t)L;
   return b + ((64 + 256 - (b & 255)) & 255);
@@ -200,7 +206,7 @@ struct Lds {
   __device__ Rot* par() const { return reinterpret_cast<Rot*>(base + G * per()); }
   __device__ double* red() const { return reinterpret_cast<double*>(par() + 2 * G); }
   __device__ double* red64(int W) const { return red() + 2 * W * G; }
-  __device__ double* Vtmp(int W) const { return red64(W) + 2 * W; }
+  __device__ double* Vtmp(int W) const { return red64(W) + 2 * kVirtWaves; }
   // progress of the pipelined localized sweeps: [W] ints, then [W][G] int64 accept counts
   __device__ int* prog(int W) const { return reinterpret_cast<int*>(Vtmp(W) + G); }
   __device__ long long* nacc(int W) const {
@@ -216,12 +222,19 @@ struct Lds {
   __device__ float4* sph(int W, int g) const {
     return reinterpret_cast<float4*>(qbuf(W, W)) + g * ((L + 7) >> 3);
   }
+  // origin of chain g's float32 work array during a global sweep (3 doubles)
+  __device__ double* orig(int W, int g) const { return reinterpret_cast<double*>(sph(W, G)) + 3 * g; }
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
-  return (size_t)G * chain_stride(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)W +
+  return (size_t)G * chain_stride(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)kVirtWaves +
          8 * (size_t)G + 4 * (size_t)((W + 1) & ~1) + 8 * (size_t)W * G + 64 + 16 +
-         8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8);
+         8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8) + 24 * (size_t)G;
+}
+
+// a localized-only launch does not use the near-pair queues, spheres and origins
+size_t sweep_lds_bytes_local(int G, int L, int W) {
+  return sweep_lds_bytes(G, L, W) - 8 * 64 * (size_t)W - 16 * (size_t)G * ((L + 7) / 8) - 24 * (size_t)G;
 }
 
 __device__ __forceinline__ void axis_atoms(const double* x64, int k, D3& A, D3& B) {
@@ -635,9 +648,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       // blocks of 8 residues for the rectangle's tiles; a tile is skipped when its
       // spheres are more than rcut apart (the last knot + 0.05 A)
       const int nb8 = (L + 7) >> 3, nres8 = 8 * nb8;
-      const float inv_nres8 = 1.0f / (float)nres8;
       const float rcut = __builtin_amdgcn_sqrtf(P.d2far) + 0.05f;
+      int pprev = 0;   // pivot of the previous proposal (0: refresh every residue)
       if (owner) {
+        // origin of the chain's float32 work array for this sweep: its middle C-beta
+        if (lane < 3) S.orig(W, wave)[lane] = atom(S.x64(wave), L / 2, 3)[lane];
         bt = fill_batch(P, 0, (uint32_t)t, (uint32_t)(P.chain_offset + my_chain), lane);
         D3 a, b;
         axis_atoms(S.x64(wave), 0, a, b);
@@ -650,25 +665,65 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       for (int k = 0; k < n; ++k) {
         const int c = k >> 1, p = (k & 1) ? c + 1 : c, M = L - p;
         const Rot* pr = S.par() + (k & 1) * G;
-        // [B] float32 C-beta of the trial conformation relative to the pivot point
-        // (the fixed residues i < p as they are, the moved ones rotated) and a
-        // bounding sphere (centroid, radius) of every block of 8 consecutive residues;
-        // the 8 residues of a block sit in 8 aligned lanes of one wavefront
-        for (int e0 = 0; e0 < nact * nres8; e0 += T) {
-          // floor((e + 1/2) / nres8) through the float reciprocal (exact for e < 2^22)
-          const int e = e0 + tid, g = (int)(((float)e + 0.5f) * inv_nres8), r = e - g * nres8;
+        // [T] for odd k, the row and column that carry the rectangle energy from pivot
+        // p-1 to p (current conformation): pair x is (x, p-1) for x < p-1, else
+        // (p-1, p + x - (p-1)); the G chains' stencils are loaded together (absent
+        // chains read the zero row).  A thread's first pair is loaded here and evaluated
+        // after [B], so that the loads overlap it.
+        double tr[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) tr[g] = 0.0;
+        float4 tq[G];
+        float tf[G];
+        double tsgn = 0.0;
+        auto transition_load = [&](int x) {
+          int i, j;
+          if (x < p - 1) { i = x; j = p - 1; tsgn = -1.0; }
+          else { i = p - 1; j = p + (x - (p - 1)); tsgn = 1.0; }
+          const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const float d2 = g < nact ? dist2_64(ld3(atom(S.x64(g), i, 3)), ld3(atom(S.x64(g), j, 3)))
+                                      : __builtin_inff();
+            tq[g] = ld_stencil(stencil_addr(row, P.zrow, d2, sp, P.d2far, tf[g]));
+          }
+        };
+        auto transition_add = [&]() {
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            tr[g] += tsgn * fixed30(catmull_rom(tq[g].x, tq[g].y, tq[g].z, tq[g].w, tf[g]));
+        };
+        auto transition = [&](int x) {
+          transition_load(x);
+          transition_add();
+        };
+        const bool tfirst = (k & 1) && tid < L - 1;
+        if (tfirst) transition_load(tid);
+        // [B] float32 C-beta of the trial conformation relative to the chain's origin
+        // for this global sweep (the fixed residues i < p as they are, the moved ones
+        // rotated) and a bounding sphere (centroid, radius) of every block of 8
+        // consecutive residues; the 8 residues of a block sit in 8 aligned lanes of one
+        // wavefront.  Residues below the previous pivot hold their committed position
+        // already (a proposal moves only residues from its pivot on), so only the blocks
+        // from that of the previous pivot are refreshed.
+        const int rb = 8 * (pprev >> 3), nrb = nres8 - rb;
+        const float inv_nrb = 1.0f / (float)nrb;
+        for (int e0 = 0; e0 < nact * nrb; e0 += T) {
+          // floor((e + 1/2) / nrb) through the float reciprocal (exact for e < 2^21)
+          const int e = e0 + tid, g = (int)(((float)e + 0.5f) * inv_nrb), r = rb + (e - g * nrb);
           const bool real = g < nact && r < L;
           float vx = 0.0f, vy = 0.0f, vz = 0.0f;
           if (real) {
-            const Rot& R = pr[g];
-            const D3 x = ld3(atom(S.x64(g), r, 3));
-            if (r < p) {
-              vx = (float)(x.x - R.a[0]); vy = (float)(x.y - R.a[1]); vz = (float)(x.z - R.a[2]);
+            if (r < pprev) {
+              const float4 v = S.w32(g)[r];
+              vx = v.x; vy = v.y; vz = v.z;
             } else {
-              const D3 v = rot_rel(R, x);
-              vx = (float)v.x; vy = (float)v.y; vz = (float)v.z;
+              const double* const o = S.orig(W, g);
+              D3 x = ld3(atom(S.x64(g), r, 3));
+              if (r >= p) x = apply_rot(pr[g], x);
+              vx = (float)(x.x - o[0]); vy = (float)(x.y - o[1]); vz = (float)(x.z - o[2]);
+              S.w32(g)[r] = make_float4(vx, vy, vz, 0.0f);
             }
-            S.w32(g)[r] = make_float4(vx, vy, vz, 0.0f);
           }
           // any centre will do (the radius is measured from it); the 0.05 A margin of the
           // tile test covers the 1-ulp hardware square root
@@ -679,6 +734,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
                                       : 0.0f);
           if (g < nact && (r & 7) == 0) S.sph(W, g)[r >> 3] = make_float4(cx, cy, cz, rad);
         }
+        pprev = p;
+        if (tfirst) transition_add();
         if (owner && k + 1 < n) {
           D3 nB;
           axis_atoms(S.x64(wave), k + 1, nA, nB);
@@ -687,9 +744,9 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         __syncthreads();
         // [C] rectangle i < p <= j (trial), and for odd k the row and column that
         // carry the rectangle energy from pivot p-1 to p (current conformation)
-        double acc[G], tr[G];
+        double acc[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) { acc[g] = 0.0; tr[g] = 0.0; }
+        for (int g = 0; g < G; ++g) acc[g] = 0.0;
         const int npairs = p * M;
         if (npairs > 0) {
           // The rectangle is cut into tiles of 8 rows (blocks I up to that of p - 1) by 8
@@ -769,27 +826,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
           }
           if (fill > 0) flush(fill);
         }
-        if (k & 1) {
-          for (int x = tid; x < L - 1; x += T) {
-            int i, j;
-            double sgn;
-            if (x < p - 1) { i = x; j = p - 1; sgn = -1.0; }
-            else { i = p - 1; j = p + (x - (p - 1)); sgn = 1.0; }
-            const float* row = P.ydev + (size_t)pair_row(i, j, L) * P.stride;
-            // the G chains' stencils are loaded together (absent chains read the zero row)
-            float4 qv[G];
-            float fv[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-              const float d2 = g < nact ? dist2_64(ld3(atom(S.x64(g), i, 3)), ld3(atom(S.x64(g), j, 3)))
-                                        : __builtin_inff();
-              qv[g] = ld_stencil(stencil_addr(row, P.zrow, d2, sp, P.d2far, fv[g]));
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-              tr[g] += sgn * fixed30(catmull_rom(qv[g].x, qv[g].y, qv[g].z, qv[g].w, fv[g]));
-          }
-        }
+        if (k & 1)
+          for (int x = tid + T; x < L - 1; x += T) transition(x);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           if (g < nact) {
@@ -931,7 +969,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
 // global (the caller splits a range where the kind changes); each instance holds
 // only its kind of sweep, and so its own register allocation.
 template <int G, int MODE>
-__global__ __launch_bounds__(512) void sweep_kernel(SweepParams P) {
+__global__ __launch_bounds__(MODE == kSweepLocal ? 768 : 512) void sweep_kernel(SweepParams P) {
   sweep_body<G, MODE>(P, blockIdx.x);
 }
 
