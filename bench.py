@@ -6,8 +6,9 @@ sweeps, sigma = 10 deg, T 1 -> 0.01 geometric over 5000 sweeps, extended-chain
 start.  One step = one alternation cycle (9 localized + 1 global sweep) of all
 chains = 10 * 600 * 1024 proposals.  Inputs are resident in HBM before timing.
 
-Prints one JSON line with proposals/s, the roofline of the sweep kernel and the
-oracle timed on the host cores (CPU baseline leg).
+Prints one JSON line with proposals/s, the roofline of the global-sweep kernel (the
+dominant one; the localized-sweep kernel's beside it) and the oracle timed on the host
+cores (CPU baseline leg).
 """
 import argparse
 import json
@@ -48,16 +49,17 @@ def code_digest(paths) -> str:
 
 
 def measured_traffic():
-    """HBM bytes per launch of the sweep kernel from the committed counter record
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None once the kernel code differs
-    from the code the counters were taken on."""
+    """HBM bytes per launch of the two sweep kernels ({"local": B, "global": B}) from
+    the committed counter record (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None
+    once the kernel code differs from the code the counters were taken on."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
         if code_digest(rec["sources"]) != rec["code_sha256"]:
             return None
-    except (OSError, ValueError, KeyError):
+        return {k: rec[k]["fetch_bytes_per_launch"] + rec[k]["write_bytes_per_launch"]
+                for k in ("local", "global")}
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def host_cores() -> int:
@@ -100,20 +102,31 @@ def schedule_work(L: int, d: int, cycle: int) -> dict:
 
 
 def executed_work(fixed: dict, counted: dict, chains: int) -> dict:
-    """Per-launch executed work: the schedule's part times the chains, plus the
-    counted global-sweep part (surviving tiles, pair tests, near pairs)."""
+    """Executed work of one step, split by kernel: the localized-sweep launch (the
+    schedule's localized pairs: two stencils and a rotation each) and the
+    global-sweep launch (the schedule's candidate tiles, transition pairs and the
+    anchor's pairs, plus the counted surviving tiles, pair tests and near pairs)."""
     loc = fixed["local_pairs"] * chains
     trans = fixed["transition_pairs"] * chains
     anch = fixed["anchor_pairs"] * chains
+    cand = fixed["candidate_tiles"] * chains
     tests = counted["pair_tests"]
     near = counted["near_pairs"]
-    stencils = 2 * loc + near + trans + anch
-    flops = (FLOPS_TEST * (tests + fixed["candidate_tiles"] * chains + 2 * loc + trans + anch)
-             + FLOPS_SPLINE * stencils + FLOPS_ROTATE * loc)
-    return {"local_pairs": loc, "candidate_tiles": fixed["candidate_tiles"] * chains,
-            "surviving_tiles": counted["tiles"], "pair_tests": tests, "near_pairs": near,
-            "transition_pairs": trans, "anchor_pairs": anch, "stencils": stencils,
-            "stencil_bytes": STENCIL_BYTES * stencils, "flops": flops}
+    st_l = 2 * loc
+    st_g = near + trans + anch
+    fl_l = FLOPS_TEST * 2 * loc + FLOPS_SPLINE * st_l + FLOPS_ROTATE * loc
+    fl_g = FLOPS_TEST * (tests + cand + trans + anch) + FLOPS_SPLINE * st_g
+    # L2 gathers: one per localized pair (its second stencil, at the proposed distance,
+    # reads the same table row right after the first and mostly the same cache line),
+    # one per stencil of the global sweep
+    return {
+        "local": {"local_pairs": loc, "stencils": st_l, "stencil_bytes": STENCIL_BYTES * st_l,
+                  "l2_gather_bytes": STENCIL_BYTES * loc, "flops": fl_l},
+        "global": {"candidate_tiles": cand, "surviving_tiles": counted["tiles"], "pair_tests": tests,
+                   "near_pairs": near, "transition_pairs": trans, "anchor_pairs": anch, "stencils": st_g,
+                   "stencil_bytes": STENCIL_BYTES * st_g, "l2_gather_bytes": STENCIL_BYTES * st_g, "flops": fl_g},
+        "step": {"stencils": st_l + st_g, "stencil_bytes": STENCIL_BYTES * (st_l + st_g), "flops": fl_l + fl_g},
+    }
 
 
 def gpu_leg(w, steps, warmup, G=0, W=0, target=None, count_work=True):
@@ -133,36 +146,49 @@ def gpu_leg(w, steps, warmup, G=0, W=0, target=None, count_work=True):
     ctx.set_target(target if target is not None else target_ref)
     info = ctx.info()
     cyc = w.global_every
+    # a step is one cycle: its localized sweeps (one launch of the localized-sweep
+    # kernel) and then its global sweeps (one launch of the global-sweep kernel), as
+    # amh_sweep(cyc) issues them; events on the launch stream around each
+    n_glob = w.n_global
+    n_loc = cyc - n_glob
     stream = torch.cuda.current_stream()
-    wev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(warmup)]
-    for e0, e1 in wev:
-        e0.record(stream)
-        ctx.sweep(cyc)
-        e1.record(stream)
+
+    def events(n):
+        return [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(n)]
+
+    def run(evs):
+        for e0, e1, e2 in evs:
+            e0.record(stream)
+            ctx.sweep(n_loc)
+            e1.record(stream)
+            ctx.sweep(n_glob)
+            e2.record(stream)
+
+    wev = events(warmup)
+    run(wev)
     torch.cuda.synchronize()
     work = torch.zeros(3, dtype=torch.int64, device=dev)
     if count_work:
         ctx.set_work_counters(work)
-    # per-launch events: one amh_sweep call per step
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    evs = events(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        ctx.sweep(cyc)
-        e1.record(stream)
+    run(evs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.set_work_counters(None)
-    launch_ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
-    warm_ms = np.array([e0.elapsed_time(e1) for e0, e1 in wev])
+    launch_ms = np.array([e0.elapsed_time(e2) for e0, e1, e2 in evs])
+    local_ms = np.array([e0.elapsed_time(e1) for e0, e1, e2 in evs])
+    global_ms = np.array([e1.elapsed_time(e2) for e0, e1, e2 in evs])
+    warm_ms = np.array([e0.elapsed_time(e2) for e0, e1, e2 in wev])
     ctx.poll()
     st = ctx.get_state()
     v = st["v"].cpu().numpy()
     cnt = st["counters"].cpu().numpy()
     ctx.close()
     wk = work.cpu().numpy()
-    return dict(wall=wall, launch_ms=launch_ms, warm_ms=warm_ms, info=info, V_ref=V_ref,
+    return dict(wall=wall, launch_ms=launch_ms, local_ms=local_ms, global_ms=global_ms, warm_ms=warm_ms,
+                info=info, V_ref=V_ref,
                 target=target, target_ref=target_ref, v=v, counters=cnt,
                 counted={"tiles": int(wk[0]), "pair_tests": int(wk[1]), "near_pairs": int(wk[2])})
 
@@ -732,14 +758,42 @@ def main():
     value = props_step * args.steps / r["wall"]
     glob, loc = pair_evals_per_cycle(w.L, w.window_d, cyc)
     dense_pairs = (glob + loc) * w.n_chains
-    # roofline of the sweep kernel on the work it executes per launch (one launch = one
-    # step): the schedule's fixed part plus the counted global-sweep part, averaged
-    # over the timed launches, over the measured average launch duration
-    launch_s = float(np.mean(r["launch_ms"])) * 1e-3
+    # rooflines on the work each kernel executes per launch (a step = one launch of the
+    # localized-sweep kernel and one of the global-sweep kernel): the schedule's fixed
+    # part plus the counted global-sweep part, averaged over the timed steps, over the
+    # kernel's average launch duration (HIP events on the launch stream)
     per_launch = {k: v / args.steps for k, v in r["counted"].items()}
     ex = executed_work(schedule_work(w.L, w.window_d, cyc), per_launch, w.n_chains)
-    achieved = ex["flops"] / launch_s
-    gather = ex["stencil_bytes"] / launch_s
+    glob_s = float(np.mean(r["global_ms"])) * 1e-3
+    loc_s = float(np.mean(r["local_ms"])) * 1e-3
+    step_s = float(np.mean(r["launch_ms"])) * 1e-3
+    G_ = r["info"]["chains_per_group"]
+    l2y = yard["l2_gather_16B"]["GB_per_s"] * 1e9 if yard else None
+
+    def roof(work, secs, kernel, traffic):
+        a = work["flops"] / secs
+        gb = work["l2_gather_bytes"] / secs
+        return {"bound": "alu", "achieved": a / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
+                "frac": a / PEAK_FP32_NONPACKED, "traffic": traffic, "traffic_unit": "bytes per launch (HBM)",
+                "kernel": kernel, "avg_launch_ms": secs * 1e3,
+                "work": "executed per launch (fixed by the schedule, plus counted in the kernel)",
+                "executed_per_launch": work,
+                "flops_per": {"pair_test": FLOPS_TEST, "stencil_spline": FLOPS_SPLINE,
+                              "local_rotation": FLOPS_ROTATE},
+                "frac_of_published_fp32": a / PEAK_FP32_PUBLISHED,
+                "gather": {"achieved_GB_per_s": gb / 1e9, "yardstick": "l2_gather_16B",
+                           "yardstick_GB_per_s": l2y / 1e9 if l2y else None,
+                           "frac": gb / l2y if l2y else None}}
+
+    traffic = measured_traffic() if w.name == sy.CFG2.name else None
+    roof_g = roof(ex["global"], glob_s, f"sweep_kernel<{G_}, 2> (global sweeps)",
+                  traffic.get("global") if traffic else None)
+    roof_g["dense_equivalent"] = {"pairs_per_launch": glob * w.n_chains,
+                                  "note": "every changed pair of the rectangle counted, culled or not; "
+                                          "not executed work"}
+    roof_l = roof(ex["local"], loc_s, f"sweep_kernel<{G_}, 1> (localized sweeps)",
+                  traffic.get("local") if traffic else None)
+    a_step = ex["step"]["flops"] / step_s
     cnt = r["counters"]
     ttt = cnt[:, 2]
     reached = ttt[ttt >= 0]
@@ -757,24 +811,11 @@ def main():
                    "noise_seed": w.noise_seed, "eps": w.eps, "accum_dtype": "f64",
                    "coord_dtype": "f64", "launch": r["info"]},
         "pair_evals_per_s": dense_pairs * args.steps / r["wall"],
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_NONPACKED / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_NONPACKED,
-                     "traffic": measured_traffic() if w.name == sy.CFG2.name else None,
-                     "traffic_unit": "bytes per launch (HBM)",
-                     "kernel": f"sweep_kernel<{r['info']['chains_per_group']}>",
-                     "avg_launch_ms": launch_s * 1e3,
-                     "work": "executed per launch (fixed by the schedule, plus counted in the kernel)",
-                     "executed_per_launch": ex,
-                     "flops_per": {"pair_test": FLOPS_TEST, "stencil_spline": FLOPS_SPLINE,
-                                   "local_rotation": FLOPS_ROTATE},
-                     "frac_of_published_fp32": achieved / PEAK_FP32_PUBLISHED,
-                     "gather": {"achieved_GB_per_s": gather / 1e9,
-                                "yardstick": "l2_gather_16B",
-                                "yardstick_GB_per_s": yard["l2_gather_16B"]["GB_per_s"] if yard else None,
-                                "frac": gather / (yard["l2_gather_16B"]["GB_per_s"] * 1e9) if yard else None},
-                     "dense_equivalent": {"pairs_per_launch": dense_pairs,
-                                          "note": "every changed pair of the rectangle counted, culled or "
-                                                  "not; not executed work"}},
+        "roofline": roof_g,
+        "roofline_local": roof_l,
+        "step_work": {"flops": ex["step"]["flops"], "stencil_bytes": ex["step"]["stencil_bytes"],
+                      "avg_step_ms": step_s * 1e3, "achieved_TFLOP_per_s": a_step / 1e12,
+                      "frac": a_step / PEAK_FP32_NONPACKED},
         "yardsticks": yard,
         "energy": {"V_ref": r["V_ref"], "target_1.05_V_ref": r["target_ref"],
                    "best_min": float(r["v"][:, 1].min()), "best_median": float(np.median(r["v"][:, 1])),

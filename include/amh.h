@@ -167,9 +167,16 @@ amh_status amh_set_work_counters(amh_ctx* ctx, int64_t* counters_dev);
  * (AMH_E_NUMERIC) raised by earlier calls. */
 amh_status amh_poll(amh_ctx* ctx);
 
-/* Launch shape chosen for the sweep kernel and the current sweep index. */
+/* Launch shape chosen for the sweep kernel (the global sweeps, and the batched
+ * launches) and the current sweep index.  amh_sweep runs a range of sweeps as one
+ * launch per run of consecutive sweeps of one kind, localized or global. */
 amh_status amh_info(amh_ctx* ctx, int32_t* chains_per_group, int32_t* waves_per_group,
                     int32_t* lds_bytes, int64_t* t);
+
+/* Launch shape of the context's localized-sweep launches: wavefronts per workgroup
+ * (consecutive localized sweeps of a workgroup's chains are pipelined over them) and
+ * LDS bytes.  Any output pointer may be NULL. */
+amh_status amh_info_local(amh_ctx* ctx, int32_t* waves_per_group, int32_t* lds_bytes);
 
 /* Energy and gradient dV/ds of B conformations, in float64 (the distogram energy
  * of Sec. 2.3 through the geometry G(s) of Sec. 2.1; the paper minimises the same

@@ -70,6 +70,9 @@ struct amh_ctx {
   double target = -INFINITY;
   int G = 1, W = 4;
   size_t lds = 0;
+  // launch shape of the localized-sweep kernel (wavefronts, LDS bytes)
+  int W_local = 4;
+  size_t lds_local = 0;
   // trace
   int n_trace = 0;
   int trace_chain[4] = {-1, -1, -1, -1};
@@ -394,6 +397,10 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   x->G = G;
   x->W = W;
   x->lds = lds;
+  // localized sweeps run with kLocalWaves wavefronts (consecutive sweeps of a block
+  // pipelined over more stages) where their LDS fits
+  x->W_local = amh::sweep_lds_bytes_local(G, cfg->L, kLocalWaves) <= kMaxLds ? kLocalWaves : W;
+  x->lds_local = amh::sweep_lds_bytes_local(G, cfg->L, x->W_local);
   const int L = cfg->L, C = cfg->n_chains, n = 2 * L;
   const int64_t P = (int64_t)L * (L - 1) / 2;
   x->stride = row_stride(cfg->n_bins);
@@ -454,10 +461,8 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
   const amh::SweepParams P0 = sweep_params(x, n_sweeps);
   const amh_config& c = x->cfg;
   const dim3 grid((c.n_chains + x->G - 1) / x->G), block(64 * x->W);
-  // localized sweeps run with kLocalWaves wavefronts (consecutive sweeps of a block
-  // pipelined over more stages) where their LDS fits
-  const int wl = amh::sweep_lds_bytes_local(x->G, c.L, kLocalWaves) <= kMaxLds ? kLocalWaves : x->W;
-  const size_t lds_l = amh::sweep_lds_bytes_local(x->G, c.L, wl);
+  const int wl = x->W_local;
+  const size_t lds_l = x->lds_local;
   // one launch per run of sweeps of one kind (localized or global), in order on the
   // stream; a launch boundary between two sweeps does not change any result
   for (int64_t t = P0.t0; t < P0.t0 + P0.n_sweeps;) {
@@ -635,6 +640,13 @@ amh_status amh_info(amh_ctx* x, int32_t* G, int32_t* W, int32_t* lds, int64_t* t
   if (W) *W = x->W;
   if (lds) *lds = (int32_t)x->lds;
   if (t) *t = x->t;
+  return AMH_OK;
+}
+
+amh_status amh_info_local(amh_ctx* x, int32_t* W, int32_t* lds) {
+  if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
+  if (W) *W = x->W_local;
+  if (lds) *lds = (int32_t)x->lds_local;
   return AMH_OK;
 }
 
