@@ -720,6 +720,7 @@ amh_status amh_destroy(amh_ctx* x) {
 namespace {
 
 constexpr int kRing = 8;   // pinned descriptor staging buffers in flight
+constexpr int kMaxRuns = 8;   // runs of one kind of sweep per call with split launches
 // launch plans: 0 = each context's own shape, then uniform (chains per group, waves)
 constexpr int kPlans = 6;
 constexpr int kPlanShape[kPlans][2] = {{0, 0}, {1, 4}, {2, 4}, {2, 8}, {4, 4}, {4, 8}};
@@ -733,6 +734,7 @@ struct amh_batch {
   struct Launch {
     int G = 1, W = 4;
     size_t lds = 0;
+    size_t lds_local = 0;   // LDS of a localized-only launch with kLocalWaves wavefronts
     int n_wg = 0;
     int2* d_map = nullptr;
   };
@@ -801,6 +803,7 @@ amh_status build_launches(amh_batch* b, int plan) {
       if (shape_of[i] != (int)s) continue;
       const amh_ctx* x = b->m[i];
       l.lds = std::max(l.lds, amh::sweep_lds_bytes(l.G, x->cfg.L, l.W));
+      l.lds_local = std::max(l.lds_local, amh::sweep_lds_bytes_local(l.G, x->cfg.L, kLocalWaves));
       const int groups = (x->cfg.n_chains + l.G - 1) / l.G;
       for (int g = 0; g < groups; ++g) items.push_back({member_cost(x), make_int2((int)i, g)});
     }
@@ -818,14 +821,23 @@ amh_status build_launches(amh_batch* b, int plan) {
   return AMH_OK;
 }
 
-template <int G>
-amh_status launch_batch(const amh_batch* b, const amh_batch::Launch& l) {
-  HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_batch_kernel<G>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)l.lds));
-  hipLaunchKernelGGL(amh::sweep_batch_kernel<G>, dim3(l.n_wg), dim3(64 * l.W), l.lds, b->stream,
-                     (const amh::SweepParams*)b->d_desc, (const int2*)l.d_map);
+template <int G, int MODE>
+amh_status launch_batch(const amh_batch* b, const amh_batch::Launch& l, const amh::SweepParams* descs,
+                        int W, size_t lds) {
+  HIP_OK(hipFuncSetAttribute((const void*)amh::sweep_batch_kernel<G, MODE>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((amh::sweep_batch_kernel<G, MODE>), dim3(l.n_wg), dim3(64 * W), lds, b->stream, descs,
+                     (const int2*)l.d_map);
   HIP_OK(hipGetLastError());
   return AMH_OK;
+}
+
+template <int MODE>
+amh_status launch_batch_mode(const amh_batch* b, const amh_batch::Launch& l, const amh::SweepParams* descs,
+                             int W, size_t lds) {
+  return l.G == 1 ? launch_batch<1, MODE>(b, l, descs, W, lds)
+         : l.G == 2 ? launch_batch<2, MODE>(b, l, descs, W, lds)
+                    : launch_batch<4, MODE>(b, l, descs, W, lds);
 }
 
 }  // namespace
@@ -846,9 +858,9 @@ amh_status amh_batch_create(amh_ctx* const* ctxs, int32_t n, amh_batch** out) {
   amh_batch* b = new amh_batch;
   b->m.assign(ctxs, ctxs + n);
   b->stream = ctxs[0]->stream;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_desc), sizeof(amh::SweepParams) * n);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_desc), sizeof(amh::SweepParams) * kMaxRuns * n);
   for (int i = 0; e == hipSuccess && i < kRing; ++i) {
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc[i]), sizeof(amh::SweepParams) * n);
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->h_desc[i]), sizeof(amh::SweepParams) * kMaxRuns * n);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
@@ -874,19 +886,61 @@ amh_status amh_batch_sweep_each(amh_batch* b, const int64_t* n_sweeps) {
     most = std::max(most, n_sweeps[i]);
   }
   if (most == 0) return AMH_OK;
-  const int slot = b->ring;
-  if (b->ev_used[slot]) HIP_OK(hipEventSynchronize(b->ev[slot]));
-  for (size_t i = 0; i < b->m.size(); ++i) b->h_desc[slot][i] = sweep_params(b->m[i], n_sweeps[i]);
-  HIP_OK(hipMemcpyAsync(b->d_desc, b->h_desc[slot], sizeof(amh::SweepParams) * b->m.size(),
-                        hipMemcpyHostToDevice, b->stream));
-  HIP_OK(hipEventRecord(b->ev[slot], b->stream));
-  b->ev_used[slot] = true;
-  b->ring = (slot + 1) % kRing;
-  for (const auto& l : b->launches) {
-    amh_status st = l.G == 1 ? launch_batch<1>(b, l) : l.G == 2 ? launch_batch<2>(b, l) : launch_batch<4>(b, l);
-    if (st != AMH_OK) return st;
+  const size_t nm = b->m.size();
+  // Split launches (localized-only and global-only kernels, one launch per run of
+  // one kind) when every member advances by the same count through the same pattern
+  // of localized and global sweeps; else one launch of the kernel that runs any
+  // sweeps.  The results are the same either way.  Descriptors go up kMaxRuns runs
+  // at a time (stream order keeps an upload behind the launches that read the last).
+  std::vector<std::pair<int64_t, bool>> runs;   // (length, global)
+  bool split = true;
+  for (size_t i = 1; i < nm && split; ++i) split = n_sweeps[i] == n_sweeps[0];
+  if (split) {
+    std::vector<amh::SweepParams> P0(nm);
+    for (size_t i = 0; i < nm; ++i) P0[i] = sweep_params(b->m[i], n_sweeps[i]);
+    for (int64_t o = 0; o < most && split; ++o) {
+      const bool g = amh::is_global(P0[0], P0[0].t0 + o);
+      for (size_t i = 1; i < nm && split; ++i) split = amh::is_global(P0[i], P0[i].t0 + o) == g;
+      if (!split) break;
+      if (!runs.empty() && runs.back().second == g) ++runs.back().first;
+      else runs.emplace_back(1, g);
+    }
   }
-  for (size_t i = 0; i < b->m.size(); ++i) b->m[i]->t += n_sweeps[i];
+  for (const auto& l : b->launches) split = split && l.lds_local <= kMaxLds;
+  if (!split) runs.assign(1, std::make_pair(most, false));
+  int64_t off = 0;
+  for (size_t r0 = 0; r0 < runs.size(); r0 += kMaxRuns) {
+    const size_t nset = std::min(runs.size() - r0, (size_t)kMaxRuns);
+    const int slot = b->ring;
+    if (b->ev_used[slot]) HIP_OK(hipEventSynchronize(b->ev[slot]));
+    for (size_t r = 0; r < nset; ++r) {
+      for (size_t i = 0; i < nm; ++i) {
+        amh::SweepParams P = sweep_params(b->m[i], n_sweeps[i]);
+        if (split) {
+          P.t0 += off;
+          P.n_sweeps = runs[r0 + r].first;
+        }
+        b->h_desc[slot][r * nm + i] = P;
+      }
+      off += runs[r0 + r].first;
+    }
+    HIP_OK(hipMemcpyAsync(b->d_desc, b->h_desc[slot], sizeof(amh::SweepParams) * nset * nm,
+                          hipMemcpyHostToDevice, b->stream));
+    HIP_OK(hipEventRecord(b->ev[slot], b->stream));
+    b->ev_used[slot] = true;
+    b->ring = (slot + 1) % kRing;
+    for (size_t r = 0; r < nset; ++r) {
+      const amh::SweepParams* descs = b->d_desc + r * nm;
+      for (const auto& l : b->launches) {
+        amh_status st = !split ? launch_batch_mode<amh::kSweepMixed>(b, l, descs, l.W, l.lds)
+                        : runs[r0 + r].second
+                            ? launch_batch_mode<amh::kSweepGlobal>(b, l, descs, l.W, l.lds)
+                            : launch_batch_mode<amh::kSweepLocal>(b, l, descs, kLocalWaves, l.lds_local);
+        if (st != AMH_OK) return st;
+      }
+    }
+  }
+  for (size_t i = 0; i < nm; ++i) b->m[i]->t += n_sweeps[i];
   return AMH_OK;
 }
 

@@ -97,7 +97,7 @@ __global__ void perturb_kernel(double* s, int64_t n_total, int n, uint32_t chain
                                uint32_t k0, uint32_t k1, double amplitude);
 template <int G, int MODE>
 __global__ void sweep_kernel(SweepParams P);
-template <int G>
+template <int G, int MODE>
 __global__ void sweep_batch_kernel(const SweepParams* descs, const int2* map);
 
 }  // namespace amh

@@ -975,11 +975,12 @@ __global__ __launch_bounds__(MODE == kSweepLocal ? 768 : 512) void sweep_kernel(
 
 // Several proteins in one launch: workgroup b runs chain group map[b].y of the
 // protein described by descs[map[b].x] (the grid is ordered by decreasing work).
-template <int G>
-__global__ __launch_bounds__(512) void sweep_batch_kernel(const SweepParams* __restrict__ descs,
-                                                          const int2* __restrict__ map) {
+// MODE as for sweep_kernel (kSweepMixed: any sweeps).
+template <int G, int MODE>
+__global__ __launch_bounds__(MODE == kSweepLocal ? 768 : 512) void sweep_batch_kernel(
+    const SweepParams* __restrict__ descs, const int2* __restrict__ map) {
   const int2 wm = map[blockIdx.x];
-  sweep_body<G, kSweepMixed>(descs[wm.x], wm.y);
+  sweep_body<G, MODE>(descs[wm.x], wm.y);
 }
 
 template __global__ void sweep_kernel<1, kSweepLocal>(SweepParams);
@@ -988,8 +989,14 @@ template __global__ void sweep_kernel<4, kSweepLocal>(SweepParams);
 template __global__ void sweep_kernel<1, kSweepGlobal>(SweepParams);
 template __global__ void sweep_kernel<2, kSweepGlobal>(SweepParams);
 template __global__ void sweep_kernel<4, kSweepGlobal>(SweepParams);
-template __global__ void sweep_batch_kernel<1>(const SweepParams*, const int2*);
-template __global__ void sweep_batch_kernel<2>(const SweepParams*, const int2*);
-template __global__ void sweep_batch_kernel<4>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<1, kSweepMixed>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<2, kSweepMixed>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<4, kSweepMixed>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<1, kSweepLocal>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<2, kSweepLocal>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<4, kSweepLocal>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<1, kSweepGlobal>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<2, kSweepGlobal>(const SweepParams*, const int2*);
+template __global__ void sweep_batch_kernel<4, kSweepGlobal>(const SweepParams*, const int2*);
 
 }  // namespace amh
