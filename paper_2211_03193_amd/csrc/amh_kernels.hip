@@ -91,41 +91,59 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
   }
 }
 
-// Float64 energy V = sum_{i<j} E_ij(|CB_i - CB_j|) of one conformation (C-beta read
-// from x64).  The pairs, in row-major order, are dealt round-robin to 64 kVirtWaves
-// virtual threads, each accumulating a Neumaier pair; the 64 virtual threads of a
+// Float64 energies V = sum_{i<j} E_ij(|CB_i - CB_j|) of nact <= G conformations of
+// one protein (C-beta of conformation g read from x0 + g xstride), side by side:
+// the pairs, in row-major order, are dealt round-robin to 64 kVirtWaves virtual
+// threads, each accumulating a Neumaier pair per conformation (the conformations'
+// table loads of a pair are in flight together); the 64 virtual threads of a
 // virtual wavefront are reduced by shuffles and the kVirtWaves partials combined in
-// order, so that V does not depend on the launch shape (wavefront w of the launch
-// runs virtual wavefronts w, w + W, ...).  red64 holds 2 kVirtWaves doubles; the
-// result is written to *V_out by thread 0 and is visible after the final barrier.
+// order, so that each V does not depend on the launch shape or on G (wavefront w of
+// the launch runs virtual wavefronts w, w + W, ...).  red64 holds 2 kVirtWaves G
+// doubles; V_out[g] is written by thread g and is visible after the final barrier.
+template <int G>
 __device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min, double w,
-                         int L, const double* __restrict__ x64, double* red64, double* V_out) {
+                         int L, const double* __restrict__ x0, size_t xstride, int nact, double* red64,
+                         double* V_out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
   constexpr int VT = 64 * kVirtWaves;
   for (int vw = wave; vw < kVirtWaves; vw += W) {
-    double sum = 0.0, cmp = 0.0;
+    double sum[G], cmp[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) { sum[g] = 0.0; cmp[g] = 0.0; }
     int i = 0, j = 1 + 64 * vw + lane;
     while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
     while (i < L - 1) {
       const float* row = table + (size_t)pair_row(i, j, L) * stride;
-      const double* a = atom(x64, i, 3);
-      const double* b = atom(x64, j, 3);
-      const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-      neumaier_add(sum, cmp, spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w));
+      double e[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double* a = atom(x0 + g * xstride, i, 3);
+        const double* b = atom(x0 + g * xstride, j, 3);
+        const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+        e[g] = g < nact ? spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w) : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) neumaier_add(sum[g], cmp[g], e[g]);
       j += VT;
       while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double so = __shfl_down(sum, o, 64), co = __shfl_down(cmp, o, 64);
-      if (lane < o) { neumaier_add(sum, cmp, so); cmp += co; }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      for (int o = 32; o > 0; o >>= 1) {
+        const double so = __shfl_down(sum[g], o, 64), co = __shfl_down(cmp[g], o, 64);
+        if (lane < o) { neumaier_add(sum[g], cmp[g], so); cmp[g] += co; }
+      }
+      if (lane == 0) { red64[2 * (vw * G + g)] = sum[g]; red64[2 * (vw * G + g) + 1] = cmp[g]; }
     }
-    if (lane == 0) { red64[2 * vw] = sum; red64[2 * vw + 1] = cmp; }
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid < nact) {
     double s = 0.0, c = 0.0;
-    for (int v = 0; v < kVirtWaves; ++v) { neumaier_add(s, c, red64[2 * v]); c += red64[2 * v + 1]; }
-    *V_out = s + c;
+    for (int v = 0; v < kVirtWaves; ++v) {
+      neumaier_add(s, c, red64[2 * (v * G + tid)]);
+      c += red64[2 * (v * G + tid) + 1];
+    }
+    V_out[tid] = s + c;
   }
   __syncthreads();
 }
@@ -160,7 +178,7 @@ __global__ void conf_energy_kernel(ConfParams P) {
   if (P.s_out)
     for (int m = tid; m < 2 * L; m += blockDim.x) P.s_out[(size_t)b * 2 * L + m] = s[m];
   if (P.table) {
-    energy64(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, x64, red64, Vs);
+    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, x64, 0, 1, red64, Vs);
     const double V = Vs[0];
     // keep_best: V becomes the current energy and replaces the best one only if lower
     // (every thread decides from the old best before it is overwritten)
@@ -206,7 +224,7 @@ struct Lds {
   __device__ Rot* par() const { return reinterpret_cast<Rot*>(base + G * per()); }
   __device__ double* red() const { return reinterpret_cast<double*>(par() + 2 * G); }
   __device__ double* red64(int W) const { return red() + 2 * W * G; }
-  __device__ double* Vtmp(int W) const { return red64(W) + 2 * kVirtWaves; }
+  __device__ double* Vtmp(int W) const { return red64(W) + 2 * kVirtWaves * G; }
   // progress of the pipelined localized sweeps: [W] ints, then [W][G] int64 accept counts
   __device__ int* prog(int W) const { return reinterpret_cast<int*>(Vtmp(W) + G); }
   __device__ long long* nacc(int W) const {
@@ -227,7 +245,7 @@ struct Lds {
 };
 
 size_t sweep_lds_bytes(int G, int L, int W) {
-  return (size_t)G * chain_stride(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)kVirtWaves +
+  return (size_t)G * chain_stride(L) + sizeof(Rot) * 2 * G + 16 * (size_t)W * G + 16 * (size_t)kVirtWaves * G +
          8 * (size_t)G + 4 * (size_t)((W + 1) & ~1) + 8 * (size_t)W * G + 64 + 16 +
          8 * 64 * (size_t)W + 16 * (size_t)G * ((L + 7) / 8) + 24 * (size_t)G;
 }
@@ -511,14 +529,15 @@ __device__ void local_sweep(const SweepParams& P, const Lds& S, int nact, int c0
 
 // Anchor: rebuild every chain's coordinates from its float64 torsions (NeRF),
 // re-anchor V in float64 and update the best state and the time-to-target.
+template <int G>
 __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int64_t t,
                        double* vbest_own, int64_t* ttt, int64_t* nanchor) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, L = P.L, W = blockDim.x >> 6;
   __syncthreads();
   if (wave < nact) nerf_chain(S.s(wave), L, S.x64(wave), lane);
   __syncthreads();
-  for (int g = 0; g < nact; ++g)
-    energy64(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, S.x64(g), S.red64(W), S.Vtmp(W) + g);
+  energy64<G>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, S.x64(0), S.per() / sizeof(double), nact,
+              S.red64(W), S.Vtmp(W));
   if (wave < nact) {
     const int g = wave, chain = c0 + g;
     const double v = S.Vtmp(W)[g];
@@ -635,7 +654,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
       }
       __syncthreads();
       t = tb;
-      if ((t % P.anchor_every) == 0) anchor(P, S, c0, nact, t - 1, &vbest_own, &ttt, &nanchor);
+      if ((t % P.anchor_every) == 0) anchor<G>(P, S, c0, nact, t - 1, &vbest_own, &ttt, &nanchor);
       continue;
     } else {
       // ---------------- global sweep, all wavefronts ----------------
@@ -934,7 +953,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams& P, const int group
         __syncthreads();
       }
     }
-    if (((t + 1) % P.anchor_every) == 0) anchor(P, S, c0, nact, t, &vbest_own, &ttt, &nanchor);
+    if (((t + 1) % P.anchor_every) == 0) anchor<G>(P, S, c0, nact, t, &vbest_own, &ttt, &nanchor);
     ++t;
   }
 
