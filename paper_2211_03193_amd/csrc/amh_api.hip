@@ -70,6 +70,8 @@ struct amh_ctx {
   double target = -INFINITY;
   int G = 1, W = 4;
   size_t lds = 0;
+  // sum of every table row's no-contact value (far_sum_kernel)
+  double vfar = 0.0;
   // launch shape of the localized-sweep kernel (wavefronts, LDS bytes)
   int W_local = 4;
   size_t lds_local = 0;
@@ -201,6 +203,7 @@ amh::ConfParams conf_base(const amh_ctx* x) {
   P.nb = x->cfg.n_bins;
   P.d_min = x->cfg.d_min;
   P.bin_w = x->cfg.bin_w;
+  P.vfar = x->vfar;
   P.err = x->err;
   return P;
 }
@@ -232,6 +235,7 @@ amh::SweepParams sweep_params(const amh_ctx* x, int64_t n_sweeps) {
   }
   P.d_min = c.d_min;
   P.bin_w = c.bin_w;
+  P.vfar = x->vfar;
   P.L = c.L;
   P.C = c.n_chains;
   P.half_window = c.window_d / 2;
@@ -425,6 +429,19 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
     hipLaunchKernelGGL(amh::ingest_kernel, dim3(blocks), dim3(256), 0, x->stream, y_dev, P,
                        cfg->n_bins, x->stride, x->table, x->ydev, x->err);
     e = hipGetLastError();
+  }
+  if (e == hipSuccess) {   // the energy of the all-far conformation, read back once
+    double* d_vfar = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&d_vfar), sizeof(double));
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(amh::far_sum_kernel, dim3(1), dim3(512), 0, x->stream, x->table, P, x->stride,
+                         cfg->n_bins, d_vfar);
+      e = hipGetLastError();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&x->vfar, d_vfar, sizeof(double), hipMemcpyDeviceToHost, x->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+      (void)hipFree(d_vfar);
+    }
   }
   if (e == hipSuccess && s0_dev)
     e = hipMemcpyAsync(x->s, s0_dev, sizeof(double) * C * n, hipMemcpyDeviceToDevice, x->stream);

@@ -20,6 +20,7 @@ struct SweepParams {
   int stride, nb;
   float inv_w, off, tmax, d2far;
   double d_min, bin_w;
+  double vfar;            // sum of every row's no-contact value (far_sum_kernel)
   // run
   int L, C, half_window, global_every, n_global, anchor_every;   // n_global >= 1
   int n_cascade, cascade_hw[3];   // extra window half-widths taken in turn with half_window
@@ -57,6 +58,7 @@ struct ConfParams {
   const float* table;
   int stride, nb;
   double d_min, bin_w;
+  double vfar;          // sum of every row's no-contact value (far_sum_kernel)
   double* V_out;        // [B]
   double* s_out;        // [B][2L]
   float* cb_out;        // [B][L][3]
@@ -92,6 +94,7 @@ inline size_t conf_lds_bytes(int L, int W) {
 __global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, float* out,
                               float* dev, unsigned int* err);
 __global__ void conf_energy_kernel(ConfParams P);
+__global__ void far_sum_kernel(const float* table, int64_t P, int stride, int nb, double* out);
 __global__ void philox_kernel(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out);
 __global__ void perturb_kernel(double* s, int64_t n_total, int n, uint32_t chain_offset, uint32_t tag,
                                uint32_t k0, uint32_t k1, double amplitude);

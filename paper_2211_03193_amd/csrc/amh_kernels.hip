@@ -92,7 +92,10 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
 }
 
 // Float64 energies V = sum_{i<j} E_ij(|CB_i - CB_j|) of nact <= G conformations of
-// one protein (C-beta of conformation g read from x0 + g xstride), side by side:
+// one protein (C-beta of conformation g read from x0 + g xstride), side by side.
+// Beyond the last knot E_ij is the row's no-contact value E_ij(inf), so V = vfar +
+// sum over the pairs inside it of (E_ij - E_ij(inf)), vfar the sum of every row's
+// no-contact value: a pair beyond the last knot costs its squared distance only.
 // the pairs, in row-major order, are dealt round-robin to 64 kVirtWaves virtual
 // threads, each accumulating a Neumaier pair per conformation (the conformations'
 // table loads of a pair are in flight together); the 64 virtual threads of a
@@ -102,10 +105,11 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
 // doubles; V_out[g] is written by thread g and is visible after the final barrier.
 template <int G>
 __device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min, double w,
-                         int L, const double* __restrict__ x0, size_t xstride, int nact, double* red64,
-                         double* V_out) {
+                         double vfar, int L, const double* __restrict__ x0, size_t xstride, int nact,
+                         double* red64, double* V_out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
   constexpr int VT = 64 * kVirtWaves;
+  const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
   for (int vw = wave; vw < kVirtWaves; vw += W) {
     double sum[G], cmp[G];
 #pragma unroll
@@ -120,7 +124,8 @@ __device__ void energy64(const float* __restrict__ table, int stride, int nb, do
         const double* a = atom(x0 + g * xstride, i, 3);
         const double* b = atom(x0 + g * xstride, j, 3);
         const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-        e[g] = g < nact ? spline64(row, sqrt(dx * dx + dy * dy + dz * dz), nb, d_min, w) : 0.0;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        e[g] = g < nact && d2 < d2far ? spline64(row, sqrt(d2), nb, d_min, w) - (double)row[nb] : 0.0;
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) neumaier_add(sum[g], cmp[g], e[g]);
@@ -143,12 +148,33 @@ __device__ void energy64(const float* __restrict__ table, int stride, int nb, do
       neumaier_add(s, c, red64[2 * (v * G + tid)]);
       c += red64[2 * (v * G + tid) + 1];
     }
+    neumaier_add(s, c, vfar);
     V_out[tid] = s + c;
   }
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
+// Sum over the P rows of the table of their no-contact value row[nb] (the energy of
+// a conformation whose pairs all lie beyond the last knot), float64 Neumaier in a
+// fixed order: one workgroup; thread t takes rows t, t + T, ...; the partials are
+// combined in thread order by thread 0.
+__global__ void far_sum_kernel(const float* __restrict__ table, int64_t P, int stride, int nb,
+                               double* __restrict__ out) {
+  __shared__ double part[2 * 1024];
+  const int tid = threadIdx.x, T = blockDim.x;
+  double s = 0.0, c = 0.0;
+  for (int64_t r = tid; r < P; r += T) neumaier_add(s, c, (double)table[r * stride + nb]);
+  part[2 * tid] = s;
+  part[2 * tid + 1] = c;
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < T; ++t) { neumaier_add(a, b, part[2 * t]); b += part[2 * t + 1]; }
+    *out = a + b;
+  }
+}
+
 // Conformation / energy kernel: one workgroup per conformation.
 __global__ void conf_energy_kernel(ConfParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -178,7 +204,7 @@ __global__ void conf_energy_kernel(ConfParams P) {
   if (P.s_out)
     for (int m = tid; m < 2 * L; m += blockDim.x) P.s_out[(size_t)b * 2 * L + m] = s[m];
   if (P.table) {
-    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, x64, 0, 1, red64, Vs);
+    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, x64, 0, 1, red64, Vs);
     const double V = Vs[0];
     // keep_best: V becomes the current energy and replaces the best one only if lower
     // (every thread decides from the old best before it is overwritten)
@@ -536,8 +562,8 @@ __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int
   __syncthreads();
   if (wave < nact) nerf_chain(S.s(wave), L, S.x64(wave), lane);
   __syncthreads();
-  energy64<G>(P.table, P.stride, P.nb, P.d_min, P.bin_w, L, S.x64(0), S.per() / sizeof(double), nact,
-              S.red64(W), S.Vtmp(W));
+  energy64<G>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, S.x64(0), S.per() / sizeof(double),
+              nact, S.red64(W), S.Vtmp(W));
   if (wave < nact) {
     const int g = wave, chain = c0 + g;
     const double v = S.Vtmp(W)[g];
