@@ -219,9 +219,10 @@ __device__ __forceinline__ double fixed30_units(float x) {
   return (double)rintf(x * 1073741824.0f);
 }
 
+// Catmull-Rom value of a padded row at distance d in float64 (inv_w = 1 / bin width).
 __device__ __forceinline__ double spline64(const float* __restrict__ row, double d, int nb,
-                                           double d_min, double w) {
-  const double t = (d - (d_min + 0.5 * w)) / w;
+                                           double d_min, double w, double inv_w) {
+  const double t = (d - (d_min + 0.5 * w)) * inv_w;
   if (t <= 0.0) return (double)row[1];
   if (t >= (double)(nb - 1)) return (double)row[nb];
   const int b = (int)floor(t);

@@ -88,7 +88,7 @@ constexpr int kSweepMixed = 0, kSweepLocal = 1, kSweepGlobal = 2;
 constexpr int kVirtWaves = 8;
 inline size_t conf_lds_bytes(int L, int W) {
   (void)W;
-  return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)kVirtWaves + 2) + 32;
+  return 8 * (2 * (size_t)L + 12 * (size_t)L + 2 * (size_t)kVirtWaves + 2) + 16 * (size_t)((L + 7) / 8) + 32;
 }
 
 __global__ void ingest_kernel(const float* y, int64_t P, int nb, int stride, float* out,

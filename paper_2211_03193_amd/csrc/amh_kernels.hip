@@ -92,65 +92,97 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, int64_t n, uint3
 }
 
 // Float64 energies V = sum_{i<j} E_ij(|CB_i - CB_j|) of nact <= G conformations of
-// one protein (C-beta of conformation g read from x0 + g xstride), side by side.
-// Beyond the last knot E_ij is the row's no-contact value E_ij(inf), so V = vfar +
-// sum over the pairs inside it of (E_ij - E_ij(inf)), vfar the sum of every row's
-// no-contact value: a pair beyond the last knot costs its squared distance only.
-// the pairs, in row-major order, are dealt round-robin to 64 kVirtWaves virtual
-// threads, each accumulating a Neumaier pair per conformation (the conformations'
-// table loads of a pair are in flight together); the 64 virtual threads of a
-// virtual wavefront are reduced by shuffles and the kVirtWaves partials combined in
-// order, so that each V does not depend on the launch shape or on G (wavefront w of
-// the launch runs virtual wavefronts w, w + W, ...).  red64 holds 2 kVirtWaves G
-// doubles; V_out[g] is written by thread g and is visible after the final barrier.
+// one protein (C-beta of conformation g read from x0 + g xstride).  Beyond the last
+// knot E_ij is the row's no-contact value E_ij(inf), so V = vfar + sum over the pairs
+// inside it of (E_ij - E_ij(inf)), vfar the sum of every row's no-contact value.
+// The pairs inside are found as in a global proposal: bounding spheres of blocks of
+// 8 residues (float32 centre and radius in sph0 + g sstride) cull the 8 x 8 tiles
+// whose spheres lie farther apart than the last knot plus 0.05 A; a surviving tile
+// is one wavefront step, a pair per lane, tested in float64.  Each pair term is
+// rounded to a multiple of 2^-40 (error < 5e-13 per pair) and summed as an integer,
+// exactly and so in any order: V does not depend on the launch shape.  acc holds G
+// 64-bit integers; V_out[g] is written by thread g, visible after the last barrier.
 template <int G>
 __device__ void energy64(const float* __restrict__ table, int stride, int nb, double d_min, double w,
-                         double vfar, int L, const double* __restrict__ x0, size_t xstride, int nact,
-                         double* red64, double* V_out) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
-  constexpr int VT = 64 * kVirtWaves;
+                         double vfar, int L, const double* __restrict__ x0, size_t xstride,
+                         float4* __restrict__ sph0, size_t sstride, int nact, long long* acc,
+                         double* V_out) {
+  const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63;
   const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
-  for (int vw = wave; vw < kVirtWaves; vw += W) {
-    double sum[G], cmp[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) { sum[g] = 0.0; cmp[g] = 0.0; }
-    int i = 0, j = 1 + 64 * vw + lane;
-    while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
-    while (i < L - 1) {
-      const float* row = table + (size_t)pair_row(i, j, L) * stride;
-      double e[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const double* a = atom(x0 + g * xstride, i, 3);
-        const double* b = atom(x0 + g * xstride, j, 3);
-        const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        e[g] = g < nact && d2 < d2far ? spline64(row, sqrt(d2), nb, d_min, w) - (double)row[nb] : 0.0;
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) neumaier_add(sum[g], cmp[g], e[g]);
-      j += VT;
-      while (j >= L && i < L - 1) { j = j - L + i + 2; ++i; }
+  const double inv_w = 1.0 / w;
+  const float rcut = (float)dfar + 0.05f;
+  const int nb8 = (L + 7) >> 3, nres8 = 8 * nb8;
+  if (tid < G) acc[tid] = 0;
+  // spheres: the 8 residues of a block in 8 aligned lanes of one wavefront
+  const float inv_nres8 = 1.0f / (float)nres8;
+  for (int e0 = 0; e0 < nact * nres8; e0 += T) {
+    const int e = e0 + tid, g = (int)(((float)e + 0.5f) * inv_nres8), r = e - g * nres8;
+    const bool real = g < nact && r < L;
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    if (real) {
+      const double* q = atom(x0 + g * xstride, r, 3);
+      vx = (float)q[0]; vy = (float)q[1]; vz = (float)q[2];
     }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      for (int o = 32; o > 0; o >>= 1) {
-        const double so = __shfl_down(sum[g], o, 64), co = __shfl_down(cmp[g], o, 64);
-        if (lane < o) { neumaier_add(sum[g], cmp[g], so); cmp[g] += co; }
-      }
-      if (lane == 0) { red64[2 * (vw * G + g)] = sum[g]; red64[2 * (vw * G + g) + 1] = cmp[g]; }
-    }
+    const float cnt = sum8(real ? 1.0f : 0.0f), inv = __builtin_amdgcn_rcpf(cnt > 1.0f ? cnt : 1.0f);
+    const float cx = sum8(vx) * inv, cy = sum8(vy) * inv, cz = sum8(vz) * inv;
+    const float rad = max8(real ? __builtin_amdgcn_sqrtf((vx - cx) * (vx - cx) + (vy - cy) * (vy - cy) +
+                                                         (vz - cz) * (vz - cz))
+                                : 0.0f);
+    if (g < nact && (r & 7) == 0) sph0[g * sstride + (r >> 3)] = make_float4(cx, cy, cz, rad);
   }
   __syncthreads();
-  if (tid < nact) {
-    double s = 0.0, c = 0.0;
-    for (int v = 0; v < kVirtWaves; ++v) {
-      neumaier_add(s, c, red64[2 * (v * G + tid)]);
-      c += red64[2 * (v * G + tid) + 1];
+  // candidate tiles (chain, row block I, column block J), I <= J, one per thread
+  long long part[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) part[g] = 0;
+  const int lr = lane >> 3, lc = lane & 7, per = nb8 * nb8;
+  const float inv_per = 1.0f / (float)per, inv_nb8 = 1.0f / (float)nb8;
+  for (int base = 0; base < nact * per; base += T) {
+    const int cand = base + tid;
+    int code = 0;
+    bool keep = false;
+    if (cand < nact * per) {
+      const int g = (int)(((float)cand + 0.5f) * inv_per), rem = cand - g * per;
+      const int I = (int)(((float)rem + 0.5f) * inv_nb8), J = rem - I * nb8;
+      if (I <= J) {
+        const float4 u = sph0[g * sstride + I], v = sph0[g * sstride + J];
+        const float dx = u.x - v.x, dy = u.y - v.y, dz = u.z - v.z, lim = rcut + u.w + v.w;
+        keep = dx * dx + dy * dy + dz * dz <= lim * lim;
+      }
+      code = (g << 20) | (I << 10) | J;
     }
-    neumaier_add(s, c, vfar);
-    V_out[tid] = s + c;
+    unsigned long long m = __ballot(keep);
+    while (m) {
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      const int cd = __builtin_amdgcn_readlane(code, l);
+      const int g = cd >> 20, i = 8 * ((cd >> 10) & 1023) + lr, j = 8 * (cd & 1023) + lc;
+      if (i < j && j < L) {
+        const double* pa = atom(x0 + g * xstride, i, 3);
+        const double* pb = atom(x0 + g * xstride, j, 3);
+        const double dx = pb[0] - pa[0], dy = pb[1] - pa[1], dz = pb[2] - pa[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < d2far) {
+          const float* row = table + (size_t)pair_row(i, j, L) * stride;
+          // distance through the hardware reciprocal square root and two Newton steps
+          const double e = spline64(row, d2 * rsqrt64(d2), nb, d_min, w, inv_w) - (double)row[nb];
+          const long long q = (long long)rint(e * 1099511627776.0);   // e 2^40
+#pragma unroll
+          for (int gg = 0; gg < G; ++gg)
+            if (gg == g) part[gg] += q;
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    long long v = part[g];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0 && g < nact && v != 0) atomicAdd(reinterpret_cast<unsigned long long*>(acc + g),
+                                                 (unsigned long long)v);
+  }
+  __syncthreads();
+  if (tid < nact) V_out[tid] = vfar + (double)acc[tid] * (1.0 / 1099511627776.0);
   __syncthreads();
 }
 
@@ -184,6 +216,7 @@ __global__ void conf_energy_kernel(ConfParams P) {
   double* x64 = s + 2 * L;                      // [12L]
   double* red64 = x64 + 12 * L;                 // [2 kVirtWaves]
   double* Vs = red64 + 2 * kVirtWaves;          // [1]
+  float4* sph = reinterpret_cast<float4*>(Vs + 2);   // [(L + 7) / 8] (16-byte aligned)
   const double* src = P.s_in ? P.s_in + (size_t)b * 2 * L : nullptr;
   for (int m = tid; m < 2 * L; m += blockDim.x) s[m] = src ? src[m] : kPi;
   __syncthreads();
@@ -204,7 +237,8 @@ __global__ void conf_energy_kernel(ConfParams P) {
   if (P.s_out)
     for (int m = tid; m < 2 * L; m += blockDim.x) P.s_out[(size_t)b * 2 * L + m] = s[m];
   if (P.table) {
-    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, x64, 0, 1, red64, Vs);
+    energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, x64, 0, sph, 0, 1,
+                reinterpret_cast<long long*>(red64), Vs);
     const double V = Vs[0];
     // keep_best: V becomes the current energy and replaces the best one only if lower
     // (every thread decides from the old best before it is overwritten)
@@ -562,8 +596,10 @@ __device__ void anchor(const SweepParams& P, const Lds& S, int c0, int nact, int
   __syncthreads();
   if (wave < nact) nerf_chain(S.s(wave), L, S.x64(wave), lane);
   __syncthreads();
+  // (the float32 work arrays hold the spheres: a global sweep no longer needs them)
   energy64<G>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, S.x64(0), S.per() / sizeof(double),
-              nact, S.red64(W), S.Vtmp(W));
+              S.w32(0), S.per() / sizeof(float4), nact, reinterpret_cast<long long*>(S.red64(W)),
+              S.Vtmp(W));
   if (wave < nact) {
     const int g = wave, chain = c0 + g;
     const double v = S.Vtmp(W)[g];
