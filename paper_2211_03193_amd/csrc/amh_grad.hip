@@ -102,6 +102,7 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
                              int stride, int nb, double d_min, double w, double* x64, double* ft,
                              double* red, double* __restrict__ g) {
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
+  const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
   if (wave == 0) nerf_chain(s, L, x64, lane);
   __syncthreads();
   // forces: wavefront per column j, lanes over the partners i
@@ -114,8 +115,13 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
       if (i == j) continue;
       const double* xi = atom(x64, i, 3);
       const double ex = jx - xi[0], ey = jy - xi[1], ez = jz - xi[2];
-      const double d = sqrt(ex * ex + ey * ey + ez * ez);
+      const double d2 = ex * ex + ey * ey + ez * ez;
       const float* row = table + (size_t)(i < j ? pair_row(i, j, L) : pair_row(j, i, L)) * stride;
+      if (d2 >= d2far) {   // beyond the last knot: E is the row's no-contact value, dE = 0
+        if (i < j) neumaier_add(vs, vc, (double)row[nb]);
+        continue;
+      }
+      const double d = sqrt(d2);
       double E, dE;
       spline64_ed(row, d, nb, d_min, w, E, dE);
       if (i < j) neumaier_add(vs, vc, E);
