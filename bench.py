@@ -767,7 +767,7 @@ def main():
     glob_s = float(np.mean(r["global_ms"])) * 1e-3
     loc_s = float(np.mean(r["local_ms"])) * 1e-3
     step_s = float(np.mean(r["launch_ms"])) * 1e-3
-    G_ = r["info"]["chains_per_group"]
+    Gg, Gl = r["info"]["global_chains_per_group"], r["info"]["local_chains_per_group"]
     l2y = yard["l2_gather_16B"]["GB_per_s"] * 1e9 if yard else None
 
     def roof(work, secs, kernel, traffic):
@@ -786,12 +786,12 @@ def main():
                            "frac": gb / l2y if l2y else None}}
 
     traffic = measured_traffic() if w.name == sy.CFG2.name else None
-    roof_g = roof(ex["global"], glob_s, f"sweep_kernel<{G_}, 2> (global sweeps)",
+    roof_g = roof(ex["global"], glob_s, f"sweep_kernel<{Gg}, 2> (global sweeps)",
                   traffic.get("global") if traffic else None)
     roof_g["dense_equivalent"] = {"pairs_per_launch": glob * w.n_chains,
                                   "note": "every changed pair of the rectangle counted, culled or not; "
                                           "not executed work"}
-    roof_l = roof(ex["local"], loc_s, f"sweep_kernel<{G_}, 1> (localized sweeps)",
+    roof_l = roof(ex["local"], loc_s, f"sweep_kernel<{Gl}, 1> (localized sweeps)",
                   traffic.get("local") if traffic else None)
     a_step = ex["step"]["flops"] / step_s
     cnt = r["counters"]

@@ -167,16 +167,21 @@ amh_status amh_set_work_counters(amh_ctx* ctx, int64_t* counters_dev);
  * (AMH_E_NUMERIC) raised by earlier calls. */
 amh_status amh_poll(amh_ctx* ctx);
 
-/* Launch shape chosen for the sweep kernel (the global sweeps, and the batched
- * launches) and the current sweep index.  amh_sweep runs a range of sweeps as one
- * launch per run of consecutive sweeps of one kind, localized or global. */
+/* Launch shape chosen for the context (chains and wavefronts per workgroup and LDS
+ * bytes of a launch that runs any sweeps: the batched launches' own-shape plan) and
+ * the current sweep index.  amh_sweep runs a range of sweeps as one launch per run of
+ * consecutive sweeps of one kind, localized or global; amh_info_launches gives their
+ * shapes. */
 amh_status amh_info(amh_ctx* ctx, int32_t* chains_per_group, int32_t* waves_per_group,
                     int32_t* lds_bytes, int64_t* t);
 
-/* Launch shape of the context's localized-sweep launches: wavefronts per workgroup
- * (consecutive localized sweeps of a workgroup's chains are pipelined over them) and
- * LDS bytes.  Any output pointer may be NULL. */
-amh_status amh_info_local(amh_ctx* ctx, int32_t* waves_per_group, int32_t* lds_bytes);
+/* Launch shapes of amh_sweep's localized-sweep launches (consecutive localized sweeps
+ * of a workgroup's chains are pipelined over its wavefronts) and global-sweep
+ * launches: chains and wavefronts per workgroup and LDS bytes.  Any output pointer
+ * may be NULL. */
+amh_status amh_info_launches(amh_ctx* ctx, int32_t* local_chains_per_group, int32_t* local_waves_per_group,
+                             int32_t* local_lds_bytes, int32_t* global_chains_per_group,
+                             int32_t* global_waves_per_group, int32_t* global_lds_bytes);
 
 /* Energy and gradient dV/ds of B conformations, in float64 (the distogram energy
  * of Sec. 2.3 through the geometry G(s) of Sec. 2.1; the paper minimises the same

@@ -108,7 +108,7 @@ def lib():
         "amh_set_work_counters": [_P, _P],
         "amh_info": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                      C.POINTER(C.c_int64)],
-        "amh_info_local": [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "amh_info_launches": [_P] + [C.POINTER(C.c_int32)] * 6,
         "amh_grad": [_P, _P, C.c_int32, _P, _P],
         "amh_minimize": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
         "amh_minimize_noalloc": [_P, _P, C.c_int32, C.POINTER(LbfgsOpts), _P, _P, _P, _P, _P],
@@ -329,10 +329,14 @@ class Context:
         g, w, l = C.c_int32(), C.c_int32(), C.c_int32()
         t = C.c_int64()
         check(lib().amh_info(self._h, C.byref(g), C.byref(w), C.byref(l), C.byref(t)))
-        wl, ll = C.c_int32(), C.c_int32()
-        check(lib().amh_info_local(self._h, C.byref(wl), C.byref(ll)))
-        return {"chains_per_group": g.value, "waves_per_group": w.value, "lds_bytes": l.value,
-                "t": t.value, "local_waves_per_group": wl.value, "local_lds_bytes": ll.value}
+        sh = [C.c_int32() for _ in range(6)]
+        check(lib().amh_info_launches(self._h, *[C.byref(v) for v in sh]))
+        out = {"chains_per_group": g.value, "waves_per_group": w.value, "lds_bytes": l.value, "t": t.value}
+        for i, kind in enumerate(("local", "global")):
+            out[f"{kind}_chains_per_group"] = sh[3 * i].value
+            out[f"{kind}_waves_per_group"] = sh[3 * i + 1].value
+            out[f"{kind}_lds_bytes"] = sh[3 * i + 2].value
+        return out
 
     def close(self) -> None:
         if self._h:

@@ -75,6 +75,9 @@ struct amh_ctx {
   // launch shape of the localized-sweep kernel (wavefronts, LDS bytes)
   int W_local = 4;
   size_t lds_local = 0;
+  // launch shape of the global-sweep kernel (chains and wavefronts per workgroup, LDS)
+  int G_global = 1, W_global = 4;
+  size_t lds_global = 0;
   // trace
   int n_trace = 0;
   int trace_chain[4] = {-1, -1, -1, -1};
@@ -405,6 +408,18 @@ amh_status amh_init(const amh_config* cfg, const float* y_dev, const double* s0_
   // pipelined over more stages) where their LDS fits
   x->W_local = amh::sweep_lds_bytes_local(G, cfg->L, kLocalWaves) <= kMaxLds ? kLocalWaves : W;
   x->lds_local = amh::sweep_lds_bytes_local(G, cfg->L, x->W_local);
+  // global sweeps of an automatically shaped context: two workgroups of two chains
+  // and four wavefronts per CU where their LDS fits, so that one workgroup runs
+  // while the other waits at a barrier
+  x->G_global = G;
+  x->W_global = W;
+  x->lds_global = lds;
+  if (cfg->chains_per_group == 0 && cfg->waves_per_group == 0 && G == 4 && W == 8 &&
+      2 * amh::sweep_lds_bytes(2, cfg->L, 4) <= kMaxLds) {
+    x->G_global = 2;
+    x->W_global = 4;
+    x->lds_global = amh::sweep_lds_bytes(2, cfg->L, 4);
+  }
   const int L = cfg->L, C = cfg->n_chains, n = 2 * L;
   const int64_t P = (int64_t)L * (L - 1) / 2;
   x->stride = row_stride(cfg->n_bins);
@@ -490,7 +505,7 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
     P.t0 = t;
     P.n_sweeps = e - t;
     const void* fn = nullptr;
-    switch (x->G) {
+    switch (glob ? x->G_global : x->G) {
       case 1: fn = glob ? (const void*)amh::sweep_kernel<1, amh::kSweepGlobal>
                         : (const void*)amh::sweep_kernel<1, amh::kSweepLocal>; break;
       case 2: fn = glob ? (const void*)amh::sweep_kernel<2, amh::kSweepGlobal>
@@ -498,10 +513,11 @@ amh_status amh_sweep(amh_ctx* x, int64_t n_sweeps) {
       default: fn = glob ? (const void*)amh::sweep_kernel<4, amh::kSweepGlobal>
                          : (const void*)amh::sweep_kernel<4, amh::kSweepLocal>; break;
     }
-    const size_t lds = glob ? x->lds : lds_l;
+    const size_t lds = glob ? x->lds_global : lds_l;
+    const dim3 gg((c.n_chains + x->G_global - 1) / x->G_global);
     HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void* args[] = {&P};
-    HIP_OK(hipLaunchKernel(fn, grid, glob ? block : dim3(64 * wl), args, lds, x->stream));
+    HIP_OK(hipLaunchKernel(fn, glob ? gg : grid, dim3(64 * (glob ? x->W_global : wl)), args, lds, x->stream));
     t = e;
   }
   HIP_OK(hipGetLastError());
@@ -660,10 +676,15 @@ amh_status amh_info(amh_ctx* x, int32_t* G, int32_t* W, int32_t* lds, int64_t* t
   return AMH_OK;
 }
 
-amh_status amh_info_local(amh_ctx* x, int32_t* W, int32_t* lds) {
+amh_status amh_info_launches(amh_ctx* x, int32_t* local_G, int32_t* local_W, int32_t* local_lds,
+                             int32_t* global_G, int32_t* global_W, int32_t* global_lds) {
   if (!x) return sfail(AMH_E_INVAL, "ctx is NULL");
-  if (W) *W = x->W_local;
-  if (lds) *lds = (int32_t)x->lds_local;
+  if (local_G) *local_G = x->G;
+  if (local_W) *local_W = x->W_local;
+  if (local_lds) *local_lds = (int32_t)x->lds_local;
+  if (global_G) *global_G = x->G_global;
+  if (global_W) *global_W = x->W_global;
+  if (global_lds) *global_lds = (int32_t)x->lds_global;
   return AMH_OK;
 }
 
