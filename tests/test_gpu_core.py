@@ -300,3 +300,31 @@ def test_wait_bound_reports_a_device_error():
     ok.sweep(10)
     ok.poll()
     ok.close()
+
+
+def test_launch_shapes():
+    """amh_sweep's launches at L = 300 with 1024 chains: an automatically shaped
+    context runs its localized sweeps in workgroups of 4 chains and 12 wavefronts
+    and its global sweeps in workgroups of 2 chains and 4 wavefronts (two per CU);
+    an explicit shape is kept for both kinds of launch."""
+    gu.say("launch shapes")
+    w = sy.CFG2.replace(total_sweeps=20)
+    _, y = gu.protein(w)
+    ctx = gu.context(w, y)
+    info = ctx.info()
+    assert (info["chains_per_group"], info["waves_per_group"]) == (4, 8)
+    assert (info["local_chains_per_group"], info["local_waves_per_group"]) == (4, 12)
+    assert (info["global_chains_per_group"], info["global_waves_per_group"]) == (2, 4)
+    assert 2 * info["global_lds_bytes"] <= 160 * 1024
+    ctx.sweep(10)
+    a = ctx.get_state()
+    ctx.close()
+    ctx = gu.context(w, y, chains_per_group=4, waves_per_group=8)
+    info = ctx.info()
+    assert (info["global_chains_per_group"], info["global_waves_per_group"]) == (4, 8)
+    ctx.sweep(10)
+    b = ctx.get_state()
+    ctx.close()
+    # the same trajectories whatever the grouping of the global launches
+    assert np.array_equal(a["s"].cpu().numpy(), b["s"].cpu().numpy())
+    assert np.array_equal(a["v"].cpu().numpy(), b["v"].cpu().numpy())
