@@ -32,8 +32,8 @@ namespace amh {
 // Pair energy and its derivative dE/dd from a padded row [y1, y0 .. y_{nb-1}, y_{nb-2}]:
 // uniform Catmull-Rom on the bin centres, flat (zero derivative) outside the knots.
 __device__ __forceinline__ void spline64_ed(const float* __restrict__ row, double d, int nb,
-                                            double d_min, double w, double& E, double& dE) {
-  const double t = (d - (d_min + 0.5 * w)) / w;
+                                            double d_min, double w, double inv_w, double& E, double& dE) {
+  const double t = (d - (d_min + 0.5 * w)) * inv_w;
   if (t <= 0.0) { E = (double)row[1]; dE = 0.0; return; }
   if (t >= (double)(nb - 1)) { E = (double)row[nb]; dE = 0.0; return; }
   const int b = (int)floor(t);
@@ -43,7 +43,7 @@ __device__ __forceinline__ void spline64_ed(const float* __restrict__ row, doubl
   const double a2 = 2.0 * q0 - 5.0 * q1 + 4.0 * q2 - q3;
   const double a3 = -q0 + 3.0 * q1 - 3.0 * q2 + q3;
   E = 0.5 * (2.0 * q1 + a1 * f + a2 * f * f + a3 * f * f * f);
-  dE = 0.5 * (a1 + 2.0 * a2 * f + 3.0 * a3 * f * f) / w;
+  dE = 0.5 * (a1 + 2.0 * a2 * f + 3.0 * a3 * f * f) * inv_w;
 }
 
 // Sum over the 64 lanes by a fixed butterfly: every lane gets the same value.
@@ -103,6 +103,7 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
                              double* red, double* __restrict__ g) {
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
   const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
+  const double inv_w = 1.0 / w;
   if (wave == 0) nerf_chain(s, L, x64, lane);
   __syncthreads();
   // forces: wavefront per column j, lanes over the partners i
@@ -121,12 +122,13 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
         if (i < j) neumaier_add(vs, vc, (double)row[nb]);
         continue;
       }
-      const double d = sqrt(d2);
+      // distance through the hardware reciprocal square root and two Newton steps
+      const double inv_d = d2 > 0.0 ? rsqrt64(d2) : 0.0, d = d2 * inv_d;
       double E, dE;
-      spline64_ed(row, d, nb, d_min, w, E, dE);
+      spline64_ed(row, d, nb, d_min, w, inv_w, E, dE);
       if (i < j) neumaier_add(vs, vc, E);
       if (d > 0.0) {
-        const double q = dE / d;
+        const double q = dE * inv_d;
         fx += q * ex; fy += q * ey; fz += q * ez;
       }
     }
@@ -175,7 +177,12 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) grad_kernel(GradParams P) {
+// Both kernels are held to two wavefronts per SIMD (at most 256 registers a lane).
+// Left free, the compiler gives the parallel NeRF scan, which one wavefront runs once
+// per evaluation, 271 registers and every kernel one wavefront per SIMD; under the
+// cap it spills a little inside that scan, and two workgroups share each CU (the
+// most their LDS allows at 400 residues), hiding the force pass's table gathers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) grad_kernel(GradParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int L = P.L;
   double* x64 = reinterpret_cast<double*>(lds);
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(256) grad_kernel(GradParams P) {
 // ---------------------------------------------------------------------------
 // One chain's L-BFGS.  Workspace rows (n = 2L doubles each): x, g, d, xn, gn, then
 // the curvature pairs S[m], Y[m] kept as a ring (oldest at `head`).
-__global__ void __launch_bounds__(256) lbfgs_kernel(LbfgsParams P) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) lbfgs_kernel(LbfgsParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int L = P.L, n = 2 * L, tid = threadIdx.x, T = blockDim.x, W = T >> 6;
   const int m = P.m, M = P.nonmonotone;
