@@ -34,6 +34,7 @@ namespace amh {
 __device__ __forceinline__ void spline64_ed(const float* __restrict__ row, double d, int nb,
                                             double d_min, double w, double inv_w, double& E, double& dE) {
   const double t = (d - (d_min + 0.5 * w)) * inv_w;
+  if (t != t) { E = t; dE = t; return; }   // a NaN distance: V turns NaN, no table index is formed
   if (t <= 0.0) { E = (double)row[1]; dE = 0.0; return; }
   if (t >= (double)(nb - 1)) { E = (double)row[nb]; dE = 0.0; return; }
   const int b = (int)floor(t);

@@ -265,3 +265,28 @@ def test_minimize_rejects_bad_options_and_handles_empty():
     V, g = ctx.grad(torch.zeros(0, 20, dtype=torch.float64, device=gu.DEV))
     assert V.numel() == 0 and g.numel() == 0
     ctx.close()
+
+
+def test_grad_nan_torsion_gives_nan_energy_and_a_numeric_error():
+    """A NaN torsion makes that conformation's V NaN (the pairs it moves are
+    evaluated with a NaN distance, which forms no table index), leaves the other
+    conformations of the launch as they are alone, and amh_poll reports
+    AMH_E_NUMERIC."""
+    gu.say("grad NaN torsion")
+    from paper_2211_03193_amd import amh
+    w = sy.CFG1.replace(L=20, n_chains=1)
+    _, y = gu.protein(w)
+    ctx = gu.context(w, y)
+    s = np.stack([sy.random_torsions(2 * w.L, 70 + b) for b in range(3)])
+    V_ok, g_ok = ctx.grad(torch.from_numpy(s[[0, 2]].copy()).to(gu.DEV))
+    ctx.poll()
+    s[1, 5] = np.nan
+    V, g = ctx.grad(torch.from_numpy(s).to(gu.DEV))
+    V = V.cpu().numpy()
+    assert np.isnan(V[1]) and np.isfinite(V[[0, 2]]).all()
+    assert np.array_equal(V[[0, 2]], V_ok.cpu().numpy())
+    assert torch.equal(g[[0, 2]], g_ok)
+    with pytest.raises(amh.AmhError) as e:
+        ctx.poll()
+    assert e.value.status == amh.E_NUMERIC
+    ctx.close()
