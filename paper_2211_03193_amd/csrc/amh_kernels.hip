@@ -218,8 +218,12 @@ __global__ void conf_energy_kernel(ConfParams P) {
   double* Vs = red64 + 2 * kVirtWaves;          // [1]
   float4* sph = reinterpret_cast<float4*>(Vs + 2);   // [(L + 7) / 8] (16-byte aligned)
   const double* src = P.s_in ? P.s_in + (size_t)b * 2 * L : nullptr;
-  for (int m = tid; m < 2 * L; m += blockDim.x) s[m] = src ? src[m] : kPi;
-  __syncthreads();
+  int bad = 0;   // a non-finite torsion: V(s) is undefined and returned as NaN
+  for (int m = tid; m < 2 * L; m += blockDim.x) {
+    s[m] = src ? src[m] : kPi;
+    bad |= !isfinite(s[m]);
+  }
+  bad = __syncthreads_or(bad);
   if (tid < 64) nerf_chain(s, L, x64, lane);
   __syncthreads();
   if (P.atoms_out) {
@@ -239,7 +243,7 @@ __global__ void conf_energy_kernel(ConfParams P) {
   if (P.table) {
     energy64<1>(P.table, P.stride, P.nb, P.d_min, P.bin_w, P.vfar, L, x64, 0, sph, 0, 1,
                 reinterpret_cast<long long*>(red64), Vs);
-    const double V = Vs[0];
+    const double V = bad ? __builtin_nan("") : Vs[0];
     // keep_best: V becomes the current energy and replaces the best one only if lower
     // (every thread decides from the old best before it is overwritten)
     const bool better = !(P.v_state && P.keep_best) || V < P.v_state[2 * b + 1];

@@ -88,6 +88,34 @@ def test_nonfinite_table_rejected():
     assert e.value.status == amh.E_NUMERIC
 
 
+def test_nonfinite_torsions_give_nan_energy():
+    """A conformation with a non-finite torsion has no energy: amh_init rejects such
+    a start with AMH_E_NUMERIC, and amh_energy returns NaN for that row (the other
+    rows as they are alone) and reports AMH_E_NUMERIC at the next amh_poll."""
+    from paper_2211_03193_amd import amh
+    gu.say("non-finite torsions")
+    w = sy.CFG1.replace(L=16, n_chains=3)
+    _, y = gu.protein(w)
+    s0 = np.stack([sy.random_torsions(2 * w.L, 90 + c) for c in range(3)])
+    bad = s0.copy()
+    bad[2, 9] = np.nan
+    with pytest.raises(amh.AmhError) as e:
+        gu.context(w, y, s0=bad)
+    assert e.value.status == amh.E_NUMERIC
+    ctx = gu.context(w, y, s0=s0)
+    V_ok, _, _ = ctx.energy(torch.from_numpy(s0[[0, 2]].copy()).to(gu.DEV))
+    ctx.poll()
+    s = s0.copy()
+    s[1, 4] = np.inf
+    V, _, _ = ctx.energy(torch.from_numpy(s).to(gu.DEV))
+    V = V.cpu().numpy()
+    assert np.isnan(V[1]) and np.array_equal(V[[0, 2]], V_ok.cpu().numpy())
+    with pytest.raises(amh.AmhError) as e:
+        ctx.poll()
+    assert e.value.status == amh.E_NUMERIC
+    ctx.close()
+
+
 SMALL = sy.Workload("small", L=20, n_chains=6, total_sweeps=40, window_d=6, global_every=3,
                     sigma_deg=25.0, T0=2.0, T1=0.05, seed=0x5EED01, protein_seed=5, noise_seed=6,
                     anchor_every=3)
