@@ -47,6 +47,9 @@ __device__ __forceinline__ void spline64_ed(const float* __restrict__ row, doubl
   dE = 0.5 * (a1 + 2.0 * a2 * f + 3.0 * a3 * f * f) * inv_w;
 }
 
+// x rounded to a multiple of 2^-44, as an integer count of 2^-44 (|x| < 2^19)
+__device__ __forceinline__ long long fixed44(double x) { return (long long)rint(x * 0x1p44); }
+
 // Sum over the 64 lanes by a fixed butterfly: every lane gets the same value.
 __device__ __forceinline__ double wave_allsum(double v) {
 #pragma unroll
@@ -105,43 +108,85 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
   const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
   const double inv_w = 1.0 / w;
+  // the C-beta forces F_k accumulate as integers (multiples of 2^-44) in the first
+  // three slots of ft[6k .. 6k+5]
+  long long* facc = reinterpret_cast<long long*>(ft);
+  for (int k = tid; k < L; k += T) facc[6 * k] = facc[6 * k + 1] = facc[6 * k + 2] = 0;
   if (wave == 0) nerf_chain(s, L, x64, lane);
   __syncthreads();
-  // forces: wavefront per column j, lanes over the partners i
+  // forces: every pair i < j once, in tiles of 64 rows (block I) by 64 columns (block
+  // J >= I) dealt to the wavefronts in turn.  Lane l holds row i = 64 I + l and at step
+  // u the column j = 64 J + ((l + u) & 63); the row's force accumulates in registers,
+  // and each column's travels with it (every step a lane takes the column sum of the
+  // lane above), so that after 64 steps lane l holds column 64 J + l's.  The tile's
+  // row and column sums, rounded to multiples of 2^-44, are added as integers: the
+  // totals do not depend on the order in which the wavefronts add them.
   double vs = 0.0, vc = 0.0;
-  for (int j = wave; j < L; j += W) {
-    const double* xj = atom(x64, j, 3);
-    const double jx = xj[0], jy = xj[1], jz = xj[2];
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int i = lane; i < L; i += 64) {
-      if (i == j) continue;
-      const double* xi = atom(x64, i, 3);
-      const double ex = jx - xi[0], ey = jy - xi[1], ez = jz - xi[2];
-      const double d2 = ex * ex + ey * ey + ez * ez;
-      const float* row = table + (size_t)(i < j ? pair_row(i, j, L) : pair_row(j, i, L)) * stride;
-      if (d2 >= d2far) {   // beyond the last knot: E is the row's no-contact value, dE = 0
-        if (i < j) neumaier_add(vs, vc, (double)row[nb]);
-        continue;
+  bool wide = false;   // a tile sum beyond the integer range (or NaN): V is returned NaN
+  const int nb64 = (L + 63) >> 6, ntile = nb64 * (nb64 + 1) / 2;
+  for (int tile = wave; tile < ntile; tile += W) {
+    int I = 0, rem = tile;
+    while (rem >= nb64 - I) { rem -= nb64 - I; ++I; }
+    const int J = I + rem, i = 64 * I + lane;
+    const double* xi = atom(x64, i < L ? i : 0, 3);
+    const double ix = xi[0], iy = xi[1], iz = xi[2];
+    double rx = 0.0, ry = 0.0, rz = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int u = 0; u < 64; ++u) {
+      const int j = 64 * J + ((lane + u) & 63);
+      if (i < j && j < L) {
+        const double* xj = atom(x64, j, 3);
+        const double ex = xj[0] - ix, ey = xj[1] - iy, ez = xj[2] - iz;
+        const double d2 = ex * ex + ey * ey + ez * ez;
+        const float* row = table + (size_t)pair_row(i, j, L) * stride;
+        if (d2 >= d2far) {   // beyond the last knot: E is the row's no-contact value, dE = 0
+          neumaier_add(vs, vc, (double)row[nb]);
+        } else {
+          // distance through the hardware reciprocal square root and two Newton steps
+          const double inv_d = d2 > 0.0 ? rsqrt64(d2) : 0.0, d = d2 * inv_d;
+          double E, dE;
+          spline64_ed(row, d, nb, d_min, w, inv_w, E, dE);
+          neumaier_add(vs, vc, E);
+          if (d > 0.0) {   // dV/dx_j = +q e, dV/dx_i = -q e
+            const double q = dE * inv_d, qx = q * ex, qy = q * ey, qz = q * ez;
+            cx += qx; cy += qy; cz += qz;
+            rx -= qx; ry -= qy; rz -= qz;
+          }
+        }
       }
-      // distance through the hardware reciprocal square root and two Newton steps
-      const double inv_d = d2 > 0.0 ? rsqrt64(d2) : 0.0, d = d2 * inv_d;
-      double E, dE;
-      spline64_ed(row, d, nb, d_min, w, inv_w, E, dE);
-      if (i < j) neumaier_add(vs, vc, E);
-      if (d > 0.0) {
-        const double q = dE * inv_d;
-        fx += q * ex; fy += q * ey; fz += q * ez;
-      }
+      const int up = (lane + 1) & 63;
+      cx = __shfl(cx, up, 64); cy = __shfl(cy, up, 64); cz = __shfl(cz, up, 64);
     }
-    fx = wave_allsum(fx); fy = wave_allsum(fy); fz = wave_allsum(fz);
-    if (lane == 0) {
-      double* o = ft + 6 * j;
-      o[0] = fx; o[1] = fy; o[2] = fz;
-      o[3] = jy * fz - jz * fy;
-      o[4] = jz * fx - jx * fz;
-      o[5] = jx * fy - jy * fx;
+    const double lim = 0x1p13;   // |tile sum| < 2^13: a residue's total stays below 2^19
+    wide = wide || !(fabs(rx) < lim && fabs(ry) < lim && fabs(rz) < lim && fabs(cx) < lim &&
+                     fabs(cy) < lim && fabs(cz) < lim);
+    if (!wide) {
+      if (i < L) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i), (unsigned long long)fixed44(rx));
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i + 1), (unsigned long long)fixed44(ry));
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i + 2), (unsigned long long)fixed44(rz));
+      }
+      const int jc = 64 * J + lane;
+      if (jc < L) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc), (unsigned long long)fixed44(cx));
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc + 1), (unsigned long long)fixed44(cy));
+        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc + 2), (unsigned long long)fixed44(cz));
+      }
     }
   }
+  __syncthreads();
+  // force and torque x_k x F_k of every residue, in place
+  for (int k = tid; k < L; k += T) {
+    const double fx = (double)facc[6 * k] * 0x1p-44, fy = (double)facc[6 * k + 1] * 0x1p-44,
+                 fz = (double)facc[6 * k + 2] * 0x1p-44;
+    const double* xk = atom(x64, k, 3);
+    const double kx = xk[0], ky = xk[1], kz = xk[2];
+    double* o = ft + 6 * k;
+    o[0] = fx; o[1] = fy; o[2] = fz;
+    o[3] = ky * fz - kz * fy;
+    o[4] = kz * fx - kx * fz;
+    o[5] = kx * fy - ky * fx;
+  }
+  if (wide) vs = __builtin_nan("");
   double V = vs + vc, z1 = 0.0, z2 = 0.0;
   block_sum3(V, z1, z2, red);   // also the barrier that publishes ft
   // suffix sums S_p, T_p (six components, one lane each, in chain order)
