@@ -31,20 +31,34 @@ namespace amh {
 
 // Pair energy and its derivative dE/dd from a padded row [y1, y0 .. y_{nb-1}, y_{nb-2}]:
 // uniform Catmull-Rom on the bin centres, flat (zero derivative) outside the knots.
-__device__ __forceinline__ void spline64_ed(const float* __restrict__ row, double d, int nb,
-                                            double d_min, double w, double inv_w, double& E, double& dE) {
-  const double t = (d - (d_min + 0.5 * w)) * inv_w;
-  if (t != t) { E = t; dE = t; return; }   // a NaN distance: V turns NaN, no table index is formed
-  if (t <= 0.0) { E = (double)row[1]; dE = 0.0; return; }
-  if (t >= (double)(nb - 1)) { E = (double)row[nb]; dE = 0.0; return; }
-  const int b = (int)floor(t);
+// t is the position in bin widths from the first centre; the four taps row[b .. b+3]
+// are gathered beforehand at b = stencil_base(t): b = 0 below the first knot (q1 =
+// row[1] is the value there) and for a NaN position, b = nb - 3 at or beyond the last
+// knot (q3 = row[nb]), else the interval of t.
+__device__ __forceinline__ int stencil_base(double t, int nb) {
+  return !(t > 0.0) ? 0 : t >= (double)(nb - 1) ? nb - 3 : (int)floor(t);
+}
+
+__device__ __forceinline__ void spline64_ed(double q0, double q1, double q2, double q3, double t, int b,
+                                            int nb, double inv_w, double& E, double& dE) {
+  if (t != t) { E = t; dE = t; return; }   // a NaN distance: V turns NaN
+  if (t <= 0.0) { E = q1; dE = 0.0; return; }
+  if (t >= (double)(nb - 1)) { E = q3; dE = 0.0; return; }
   const double f = t - (double)b;
-  const double q0 = row[b], q1 = row[b + 1], q2 = row[b + 2], q3 = row[b + 3];
   const double a1 = -q0 + q2;
   const double a2 = 2.0 * q0 - 5.0 * q1 + 4.0 * q2 - q3;
   const double a3 = -q0 + 3.0 * q1 - 3.0 * q2 + q3;
   E = 0.5 * (2.0 * q1 + a1 * f + a2 * f * f + a3 * f * f * f);
   dE = 0.5 * (a1 + 2.0 * a2 * f + 3.0 * a3 * f * f) * inv_w;
+}
+
+typedef __attribute__((address_space(1))) const float gfloat;
+
+// integer add to an LDS word through an LDS pointer (a generic-pointer atomic would be a
+// flat operation, which the compiler then waits on together with the table gathers)
+__device__ __forceinline__ void lds_add(long long* p, long long v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(3))) long long*)p, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // x rounded to a multiple of 2^-44, as an integer count of 2^-44 (|x| < 2^19)
@@ -108,6 +122,9 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, W = T >> 6;
   const double dfar = d_min + w * ((double)nb - 0.5), d2far = dfar * dfar;   // the last knot
   const double inv_w = 1.0 / w;
+  // the table through a global-memory pointer, so that its gathers wait only on their own
+  // counter and not on the LDS traffic of the same steps
+  const gfloat* gtable = (const gfloat*)table;
   // the C-beta forces F_k accumulate as integers (multiples of 2^-44) in the first
   // three slots of ft[6k .. 6k+5]
   long long* facc = reinterpret_cast<long long*>(ft);
@@ -124,6 +141,10 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
   double vs = 0.0, vc = 0.0;
   bool wide = false;   // a tile sum beyond the integer range (or NaN): V is returned NaN
   const int nb64 = (L + 63) >> 6, ntile = nb64 * (nb64 + 1) / 2;
+  // retire every memory operation before the tiles (the NeRF's spill stores among them),
+  // so that inside the tiles only the table gathers are counted and each step waits for
+  // the gather of the pair it evaluates, not for the one issued for the next step
+  __builtin_amdgcn_s_waitcnt(0);
   for (int tile = wave; tile < ntile; tile += W) {
     int I = 0, rem = tile;
     while (rem >= nb64 - I) { rem -= nb64 - I; ++I; }
@@ -131,45 +152,69 @@ __device__ double value_grad(const double* __restrict__ s, int L, const float* _
     const double* xi = atom(x64, i < L ? i : 0, 3);
     const double ix = xi[0], iy = xi[1], iz = xi[2];
     double rx = 0.0, ry = 0.0, rz = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
-    for (int u = 0; u < 64; ++u) {
+    // step u's partner, distance, stencil base and taps; issued one step ahead of its
+    // evaluation so that the table gather overlaps the previous pair (an absent pair
+    // reads row 0, a far one the taps ending at its no-contact value)
+    struct Pair {
+      double ex, ey, ez, inv_d, t;
+      int b;
+      bool real, near;
+      float q0, q1, q2, q3;
+    };
+    auto prep = [&](int u) {
+      Pair a;
       const int j = 64 * J + ((lane + u) & 63);
-      if (i < j && j < L) {
-        const double* xj = atom(x64, j, 3);
-        const double ex = xj[0] - ix, ey = xj[1] - iy, ez = xj[2] - iz;
-        const double d2 = ex * ex + ey * ey + ez * ez;
-        const float* row = table + (size_t)pair_row(i, j, L) * stride;
-        if (d2 >= d2far) {   // beyond the last knot: E is the row's no-contact value, dE = 0
-          neumaier_add(vs, vc, (double)row[nb]);
-        } else {
-          // distance through the hardware reciprocal square root and two Newton steps
-          const double inv_d = d2 > 0.0 ? rsqrt64(d2) : 0.0, d = d2 * inv_d;
-          double E, dE;
-          spline64_ed(row, d, nb, d_min, w, inv_w, E, dE);
-          neumaier_add(vs, vc, E);
-          if (d > 0.0) {   // dV/dx_j = +q e, dV/dx_i = -q e
-            const double q = dE * inv_d, qx = q * ex, qy = q * ey, qz = q * ez;
-            cx += qx; cy += qy; cz += qz;
-            rx -= qx; ry -= qy; rz -= qz;
-          }
+      a.real = i < j && j < L;
+      const double* xj = atom(x64, a.real ? j : 0, 3);
+      a.ex = xj[0] - ix; a.ey = xj[1] - iy; a.ez = xj[2] - iz;
+      const double d2 = a.ex * a.ex + a.ey * a.ey + a.ez * a.ez;
+      a.near = a.real && !(d2 >= d2far);   // a NaN distance is evaluated, so V turns NaN
+      // distance through the hardware reciprocal square root and two Newton steps
+      a.inv_d = a.near && d2 > 0.0 ? rsqrt64(d2) : 0.0;
+      a.t = a.near ? (d2 * a.inv_d - (d_min + 0.5 * w)) * inv_w : (double)nb;
+      a.b = stencil_base(a.t, nb);
+      const gfloat* row = gtable + (size_t)(a.real ? pair_row(i, j, L) : 0) * stride + a.b;
+      a.q0 = row[0]; a.q1 = row[1]; a.q2 = row[2]; a.q3 = row[3];
+      return a;
+    };
+    auto eval = [&](const Pair& a) {
+      if (a.real) {
+        double E = (double)a.q3, dE = 0.0;   // beyond the last knot: the no-contact value
+        if (a.near)
+          spline64_ed((double)a.q0, (double)a.q1, (double)a.q2, (double)a.q3, a.t, a.b, nb, inv_w, E, dE);
+        neumaier_add(vs, vc, E);
+        if (a.inv_d > 0.0) {   // dV/dx_j = +q e, dV/dx_i = -q e
+          const double q = dE * a.inv_d, qx = q * a.ex, qy = q * a.ey, qz = q * a.ez;
+          cx += qx; cy += qy; cz += qz;
+          rx -= qx; ry -= qy; rz -= qz;
         }
       }
       const int up = (lane + 1) & 63;
       cx = __shfl(cx, up, 64); cy = __shfl(cy, up, 64); cz = __shfl(cz, up, 64);
+    };
+    // two records in turn, so that no gathered value is copied (u = 64 prepares a pair
+    // that is not evaluated)
+    Pair A = prep(0);
+    for (int u = 0; u < 64; u += 2) {
+      const Pair B = prep(u + 1);
+      eval(A);
+      A = prep(u + 2);
+      eval(B);
     }
     const double lim = 0x1p13;   // |tile sum| < 2^13: a residue's total stays below 2^19
     wide = wide || !(fabs(rx) < lim && fabs(ry) < lim && fabs(rz) < lim && fabs(cx) < lim &&
                      fabs(cy) < lim && fabs(cz) < lim);
     if (!wide) {
       if (i < L) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i), (unsigned long long)fixed44(rx));
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i + 1), (unsigned long long)fixed44(ry));
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * i + 2), (unsigned long long)fixed44(rz));
+        lds_add(facc + 6 * i, fixed44(rx));
+        lds_add(facc + 6 * i + 1, fixed44(ry));
+        lds_add(facc + 6 * i + 2, fixed44(rz));
       }
       const int jc = 64 * J + lane;
       if (jc < L) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc), (unsigned long long)fixed44(cx));
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc + 1), (unsigned long long)fixed44(cy));
-        atomicAdd(reinterpret_cast<unsigned long long*>(facc + 6 * jc + 2), (unsigned long long)fixed44(cz));
+        lds_add(facc + 6 * jc, fixed44(cx));
+        lds_add(facc + 6 * jc + 1, fixed44(cy));
+        lds_add(facc + 6 * jc + 2, fixed44(cz));
       }
     }
   }
