@@ -191,7 +191,11 @@ amh_status amh_info_launches(amh_ctx* ctx, int32_t* local_chains_per_group, int3
  *   s_dev      [B][2L] torsions, or NULL for the context's current chains (B must
  *              equal n_chains);
  *   V_out_dev  [B] or NULL;  g_out_dev [B][2L] or NULL (not both NULL).
- * Non-finite energies raise AMH_E_NUMERIC at the next amh_poll. */
+ * The results are reproducible bit for bit (the forces are summed as integer
+ * multiples of 2^-44).  A conformation with a non-finite torsion, or whose pair forces
+ * add up to 2^13 or more within one block of 64 x 64 residue pairs, gets V = NaN (its
+ * g is then unspecified).  Non-finite energies raise AMH_E_NUMERIC at the next
+ * amh_poll. */
 amh_status amh_grad(amh_ctx* ctx, const double* s_dev, int32_t B, double* V_out_dev,
                     double* g_out_dev);
 
