@@ -290,3 +290,27 @@ def test_grad_nan_torsion_gives_nan_energy_and_a_numeric_error():
         ctx.poll()
     assert e.value.status == amh.E_NUMERIC
     ctx.close()
+
+
+def test_grad_forces_beyond_the_integer_range_give_nan():
+    """Forces that reach 2^13 within one 64 x 64 block of pairs (a finite but steep
+    table: bins alternating between 0 and 1e4) would overflow the gradient's integer
+    force sums: amh_grad returns V = NaN for such a conformation and amh_poll reports
+    AMH_E_NUMERIC, while the energy alone (amh_energy) stays finite."""
+    gu.say("grad forces beyond the integer range")
+    from paper_2211_03193_amd import amh
+    w = sy.CFG1.replace(L=20, n_chains=1)
+    s_ref, y = gu.protein(w)
+    y = np.zeros_like(y)
+    y[:, 1::2] = 1.0e4
+    ctx = gu.context(w, y)
+    s = torch.from_numpy(np.ascontiguousarray(s_ref[None])).to(gu.DEV)
+    Ve, _, _ = ctx.energy(s)
+    ctx.poll()
+    assert np.isfinite(Ve.cpu().numpy()).all()
+    V, _ = ctx.grad(s)
+    assert np.isnan(V.cpu().numpy()).all()
+    with pytest.raises(amh.AmhError) as e:
+        ctx.poll()
+    assert e.value.status == amh.E_NUMERIC
+    ctx.close()
